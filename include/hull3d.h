@@ -1,0 +1,103 @@
+/*
+ * hull3d.h -- C ABI of the MI355X (gfx950) divide-and-conquer 3-d convex hull.
+ *
+ * The method is the paper's: points sorted by x (Sec. 2), each block's lower
+ * hull kept as a "movie" -- the time-ordered insert/delete events of a 2-d
+ * kinetic hull, one event per 3-d face (Sec. 2, the kinetic reformulation) --
+ * and movies merged pairwise, level by level, bottom-up (Sec. 2, the movie
+ * array and merge step; Sec. 3, Fig. "main_loop_figure" and Fig.
+ * "kernel_variables").  The upper hull is the lower hull of the points with z
+ * negated.  All predicates are exact on the integer lattice, with ties broken
+ * by a symbolic perturbation indexed by the input position i:
+ *   (x + e1*i, y + e2*i^2, z + e3*i^3),  1 >> e1 >> e2 >> e3 > 0,
+ * so the result is the unique face set of the perturbed points' hull (every
+ * face a triangle, F = 2V - 4; degenerate inputs give one specific
+ * triangulation, possibly with zero-area faces).
+ *
+ * Conventions (all entry points):
+ *  - Pointers named d_* are device pointers owned by the caller.  The library
+ *    allocates nothing and keeps no state between calls.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
+ *    default stream).  The return value reports argument errors and launch
+ *    failures only; errors that depend on the data are written to d_info[0]
+ *    on the device.
+ *  - Points are int32 (x, y, z) rows, C-contiguous [n, 3], |coord| <= 2^29,
+ *    n <= 2^26.
+ *  - Faces are int32 rows of input indices (0-based), oriented counter-
+ *    clockwise seen from outside (outward right-hand normal).  Row order is
+ *    unspecified.  n < 3 gives no face; n = 3 gives the triangle twice, once
+ *    per orientation.
+ *  - Calls on different streams are independent if each has its own
+ *    workspace.
+ */
+#ifndef HULL3D_H
+#define HULL3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (return values and d_info[0]). */
+#define HULL_OK 0
+#define HULL_EINVAL (-1)     /* null pointer, n out of range, capacity < 2n */
+#define HULL_EWORKSPACE (-2) /* workspace smaller than hull_workspace_bytes() */
+#define HULL_ERANGE (-3)     /* some |coordinate| > 2^29 (reported in d_info[0]) */
+#define HULL_EHIP (-4)       /* HIP runtime or launch failure */
+#define HULL_EINTERNAL (-5)  /* an internal consistency bound tripped (d_info[0]) */
+
+/* Static description of a status code. */
+const char* hull_strerror(int32_t code);
+
+/* Bytes of device workspace that hull_lower / hull_full need for n points
+ * (host, synchronous).  flags: reserved, pass 0. */
+int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes);
+
+/* Lower hull: the faces whose outward normal points to negative z (under the
+ * perturbation; every face is lower or upper).
+ *   d_xyz   device int32 [n, 3]                    (read)
+ *   d_faces device int32 [cap, 3], cap >= 2n      (written: first F rows)
+ *   d_info  device int64 [2]: status, F           (written)
+ *   d_ws    device workspace of ws_bytes bytes    (scratch)
+ * The kinetic merge of the paper, run once (Sec. 2; Sec. 3). */
+int32_t hull_lower(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                   void* d_ws, size_t ws_bytes, void* stream);
+
+/* Full hull: lower faces followed by upper faces, F = 2V - 4 (n >= 3).  The
+ * upper faces are the lower faces of (x, y, -z) with the z perturbation
+ * negated too, so both halves close into one surface. */
+int32_t hull_full(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, void* stream);
+
+/* hull_full, with HIP events recorded on `stream` at phase boundaries, for
+ * timing each kernel phase:
+ *   events[0]              on entry
+ *   events[1]              after the sort
+ *   events[2k], [2k+1]     around the merge kernel of level k = 1..L,
+ *                          L = ceil(log2 n)
+ *   events[2L+2]           after the face extraction
+ * `events` is a host array of nevents >= 2L+3 hipEvent_t handles that the
+ * caller created (and destroys); otherwise the same as hull_full. */
+int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
+                        int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream,
+                        void* const* events, int32_t nevents);
+
+/* Intermediate movies, for inspection and tests: sorts, runs `level` merge
+ * levels (level < 0: all) of run 0 (lower) or 1 (upper) and writes, for
+ * every block of width 2^level from rank 0, its movie events at offset
+ * 2 * (block start):
+ *   d_ev        device int32 [2n, 4]: (left, middle, right rank, is_insertion)
+ *   d_block_len device int32 [n]: event count at each block start
+ *   d_order     device int32 [n]: input index of each rank
+ * Same workspace as hull_full. */
+int32_t hull_movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,
+                    int32_t* d_block_len, int32_t* d_order, int64_t* d_info, void* d_ws,
+                    size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HULL3D_H */

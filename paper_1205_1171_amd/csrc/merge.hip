@@ -1,0 +1,518 @@
+// Bottom-up merge levels of the kinetic hull (Sec. 2: the movie array and the
+// merge step; Sec. 3: Fig. "main_loop_figure", the level loop with ping-pong
+// event arrays, and Fig. "kernel_variables", the block offsets of a merge).
+//
+// Movie of a block [s, e) of ranks: its events, time-ordered, stored at slots
+// [2s, 2s + len) of the level's event array (at most 2 events per point, the
+// paper's two slots per point).  An event is the face (a, w, b) whose middle
+// vertex w enters or leaves the chain, plus the standard part of its time.
+//
+// Unlike the paper (a movie of bare point indices, with the point's own
+// prev/next links replayed and rewound), every event here carries its face.
+// The merge then needs no rewind pass: the -inf chains live in their own link
+// arrays (pv0/nx0), merging two of them is one splice at the -inf bridge, and
+// the working links (pv/nx) of each level start as a copy of them.
+//
+// Merge of L = [s, m) and R = [m, e) (the kinetic bridge walk):
+//   1. bridge at t = -inf: u = m-1, v = m, walk to the lower common tangent of
+//      the two xy chains;
+//   2. event loop: candidates are the next L event, the next R event and the
+//      four bridge moves (nx(u) enters, u leaves, pv(v) enters, v leaves);
+//      take the earliest strictly after the last event in (time, rank
+//      triple) order; L events left of u and R events right of v go to the
+//      output, every child event updates its child's chain, bridge moves are
+//      output events of the merged chain;
+//   3. splice the -inf chains at the -inf bridge.
+#include <algorithm>
+
+#include "common.hpp"
+#include "predicates.hpp"
+
+namespace hull {
+
+struct Cand {
+  Tri t;
+  double st;  // standard part of tau (NaN: not covered by the fast path)
+  int kind;   // 1 insertion, 0 deletion
+};
+
+struct RunPtrs {
+  const int4* pts;
+  int* pv0;
+  int* nx0;
+  int* pv;
+  int* nx;
+  const Event* ev_in;
+  const double* tau_in;
+  const int* len_in;
+  Event* ev_out;
+  double* tau_out;
+  int* len_out;
+  int zs;
+};
+
+struct LevelArgs {
+  RunPtrs run[2];
+  Header* h;
+  int64_t n;
+  int64_t half;   // size of a left block
+  int64_t width;  // size of a merged block
+  int64_t merges; // merges per run
+};
+
+// Exact (time, rank triple) order of two distinct-or-equal events.
+__device__ __noinline__ int ev_cmp_exact(const int4* pts, const Cand& A, const Cand& B, int zs) {
+  Coef ca, cb;
+  coef_of(pts[A.t.a], pts[A.t.w], pts[A.t.b], zs, ca);
+  coef_of(pts[B.t.a], pts[B.t.w], pts[B.t.b], zs, cb);
+  int s = tau_cmp_exact(ca, cb);
+  if (s) return s;
+  if (A.t.a != B.t.a) return A.t.a < B.t.a ? -1 : 1;
+  if (A.t.w != B.t.w) return A.t.w < B.t.w ? -1 : 1;
+  if (A.t.b != B.t.b) return A.t.b < B.t.b ? -1 : 1;
+  return 0;
+}
+
+__device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand& B, int zs) {
+  if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
+  int s = std_cmp(A.st, B.st);
+  if (s) return s;
+  return ev_cmp_exact(pts, A, B, zs);
+}
+
+// Perturbed sign of D(a, b, c) (xy orientation).
+__device__ __forceinline__ int d_sign(int4 P, int4 Q, int4 R) {
+  int64_t D0 = ((int64_t)Q.x - P.x) * ((int64_t)R.y - P.y) -
+               ((int64_t)R.x - P.x) * ((int64_t)Q.y - P.y);
+  if (D0) return D0 > 0 ? 1 : -1;
+  Coef c;
+  coef_of(P, Q, R, 1, c);
+  return c.dsign;
+}
+
+__device__ __forceinline__ Cand make_cand(const int4* pts, int a, int w, int b, int4 A, int4 W,
+                                          int4 B, int kind, int zs) {
+  Cand c;
+  c.t = Tri{a, w, b};
+  c.kind = kind;
+  c.st = tau_std(A, W, B, zs);
+  return c;
+}
+
+__device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int64_t e) {
+  const int4* pts = R.pts;
+  int* pv = R.pv;
+  int* nx = R.nx;
+  const int zs = R.zs;
+  const int nL = R.len_in[s], nR = R.len_in[m];
+  const Event* Lev = R.ev_in + 2 * s;
+  const Event* Rev = R.ev_in + 2 * m;
+  const double* Ltau = R.tau_in + 2 * s;
+  const double* Rtau = R.tau_in + 2 * m;
+  Event* out = R.ev_out + 2 * s;
+  double* out_tau = R.tau_out + 2 * s;
+  const int64_t cap = 2 * (e - s);
+
+  // 1. bridge at t = -inf
+  int u = (int)m - 1, v = (int)m;
+  int4 Pu = pts[u], Pv = pts[v];
+  for (int guard = 0;; ++guard) {
+    if (guard > 2 * (e - s) + 4) {
+      atomicCAS(&h->err, 0, HULL_EINTERNAL);
+      return;
+    }
+    int w = R.nx0[v];
+    if (w != kNil) {
+      int4 Pw = pts[w];
+      if (d_sign(Pu, Pv, Pw) < 0) {
+        v = w;
+        Pv = Pw;
+        continue;
+      }
+    }
+    w = R.pv0[u];
+    if (w != kNil) {
+      int4 Pw = pts[w];
+      if (d_sign(Pw, Pu, Pv) < 0) {
+        u = w;
+        Pu = Pw;
+        continue;
+      }
+    }
+    break;
+  }
+  const int u0 = u, v0 = v;
+
+  // 2. event loop
+  int i = 0, j = 0, k = 0;
+  bool haveT = false;
+  Cand T;
+  T.t = Tri{-1, -1, -1};
+  T.st = 0.0;
+  T.kind = 0;
+  const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
+  for (int64_t it = 0;; ++it) {
+    if (it > iter_cap) {
+      atomicCAS(&h->err, 0, HULL_EINTERNAL);
+      break;
+    }
+    Cand c[6];
+    bool ok[6];
+    if (i < nL) {
+      Event E = Lev[i];
+      c[0].t = Tri{E.a, E.w, E.b};
+      c[0].kind = E.kind;
+      c[0].st = Ltau[i];
+      ok[0] = true;
+    } else {
+      ok[0] = false;
+    }
+    if (j < nR) {
+      Event E = Rev[j];
+      c[1].t = Tri{E.a, E.w, E.b};
+      c[1].kind = E.kind;
+      c[1].st = Rtau[j];
+      ok[1] = true;
+    } else {
+      ok[1] = false;
+    }
+    int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
+    ok[2] = nu != kNil;
+    ok[3] = pu != kNil;
+    ok[4] = pvv != kNil;
+    ok[5] = nv != kNil;
+    if (ok[2]) c[2] = make_cand(pts, u, nu, v, Pu, pts[nu], Pv, 1, zs);
+    if (ok[3]) c[3] = make_cand(pts, pu, u, v, pts[pu], Pu, Pv, 0, zs);
+    if (ok[4]) c[4] = make_cand(pts, u, pvv, v, Pu, pts[pvv], Pv, 1, zs);
+    if (ok[5]) c[5] = make_cand(pts, u, v, nv, Pu, Pv, pts[nv], 0, zs);
+    int best = -1;
+    for (int l = 0; l < 6; ++l) {
+      if (!ok[l]) continue;
+      if (haveT && ev_cmp(pts, c[l], T, zs) <= 0) continue;
+      if (best < 0 || ev_cmp(pts, c[l], c[best], zs) < 0) best = l;
+    }
+    if (best < 0) break;
+    T = c[best];
+    haveT = true;
+    bool emit = false;
+    if (best <= 1) {
+      const Tri& t = T.t;
+      emit = best == 0 ? (t.w < u) : (t.w > v);
+      if (T.kind) {  // insertion into the child's chain
+        nx[t.a] = t.w;
+        pv[t.b] = t.w;
+        pv[t.w] = t.a;
+        nx[t.w] = t.b;
+      } else {  // deletion
+        nx[t.a] = t.b;
+        pv[t.b] = t.a;
+      }
+      if (best == 0) ++i; else ++j;
+    } else {
+      emit = true;
+      if (best == 2) { u = nu; Pu = pts[u]; }
+      else if (best == 3) { u = pu; Pu = pts[u]; }
+      else if (best == 4) { v = pvv; Pv = pts[v]; }
+      else { v = nv; Pv = pts[v]; }
+    }
+    if (emit) {
+      if (k >= cap) {
+        atomicCAS(&h->err, 0, HULL_EINTERNAL);
+        break;
+      }
+      out[k] = Event{T.t.a, T.t.w, T.t.b, T.kind};
+      out_tau[k] = T.st;
+      ++k;
+    }
+  }
+  // 3. splice the -inf chains
+  R.nx0[u0] = v0;
+  R.pv0[v0] = u0;
+  R.len_out[s] = k;
+}
+
+__global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
+  if (A.h->err) return;
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= 2 * A.merges) return;
+  int r = g >= A.merges ? 1 : 0;
+  int64_t q = g - r * A.merges;
+  if (!A.run[r].pts) return;
+  int64_t s = q * A.width, m = s + A.half, e = std::min(s + A.width, A.n);
+  merge_one(A.run[r], A.h, s, m, e);
+}
+
+// The unpaired trailing block of a level keeps its movie: copy it across.
+__global__ void __launch_bounds__(256) k_passthrough(LevelArgs A, int64_t s) {
+  int r = blockIdx.y;
+  const RunPtrs& R = A.run[r];
+  if (!R.pts) return;
+  int len = R.len_in[s];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < len;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
+    R.tau_out[2 * s + q] = R.tau_in[2 * s + q];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) R.len_out[s] = len;
+}
+
+__global__ void __launch_bounds__(256) k_init_links(int* pv0, int* nx0, int* len, int64_t n) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    pv0[p] = kNil;
+    nx0[p] = kNil;
+    len[p] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_copy_links(const int* __restrict__ pv0,
+                                                    const int* __restrict__ nx0,
+                                                    int* __restrict__ pv, int* __restrict__ nx,
+                                                    int64_t n) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    pv[p] = pv0[p];
+    nx[p] = nx0[p];
+  }
+}
+
+// Faces from the final movies: event (a, w, b) gives the face with the
+// middle vertex w; an insertion has D(a, w, b) < 0, a deletion D > 0.  Lower
+// faces need D < 0 for an outward orientation, upper faces D > 0.
+__global__ void __launch_bounds__(256)
+    k_extract(const Event* __restrict__ evL, const int* lenL, const Event* __restrict__ evU,
+              const int* lenU, const int4* __restrict__ pts, int32_t* __restrict__ faces,
+              int64_t cap, int64_t* info, const Header* h) {
+  int nL = evL ? *lenL : 0, nU = evU ? *lenU : 0;
+  int64_t total = (int64_t)nL + nU;
+  const bool over = total > cap;
+  if (over || h->err) total = 0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    bool lower = q < nL;
+    Event E = lower ? evL[q] : evU[q - nL];
+    bool keep = lower ? E.kind == 1 : E.kind == 0;
+    int a = pts[E.a].w, w = pts[E.w].w, b = pts[E.b].w;
+    faces[3 * q + 0] = a;
+    faces[3 * q + 1] = keep ? w : b;
+    faces[3 * q + 2] = keep ? b : w;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    info[0] = h->err ? h->err : (over ? HULL_EINTERNAL : 0);
+    info[1] = total;
+  }
+}
+
+__global__ void k_info_small(int64_t* info, const Header* h) {
+  if (threadIdx.x == 0) {
+    info[0] = h ? h->err : 0;
+    info[1] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_export_movies(const Event* __restrict__ ev, const int* __restrict__ len,
+                    const int4* __restrict__ pts, int64_t n, int64_t width, int32_t* d_ev,
+                    int32_t* d_block_len, int32_t* d_order) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    d_order[p] = pts[p].w;
+    bool start = p % width == 0;
+    d_block_len[p] = start ? len[p] : 0;
+  }
+  for (int64_t s = 0; s < n; s += width) {
+    int L = len[s];
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L;
+         q += (int64_t)gridDim.x * blockDim.x) {
+      Event E = ev[2 * s + q];
+      d_ev[4 * (2 * s + q) + 0] = E.a;
+      d_ev[4 * (2 * s + q) + 1] = E.w;
+      d_ev[4 * (2 * s + q) + 2] = E.b;
+      d_ev[4 * (2 * s + q) + 3] = E.kind;
+    }
+  }
+}
+
+static int levels_for(int64_t n) {
+  int L = 0;
+  while ((int64_t(1) << L) < n) ++L;
+  return L;
+}
+
+static unsigned grid_for(int64_t work, int64_t cap_blocks = 4096) {
+  int64_t b = (work + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > cap_blocks) b = cap_blocks;
+  return (unsigned)b;
+}
+
+// Runs `levels` merge levels of the selected runs; returns the buffer index
+// holding the final movies.
+static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bool lower,
+                          bool upper, int levels, int* final_buf, hipEvent_t* events) {
+  Header* h = (Header*)(ws + pl.header);
+  LevelArgs A{};
+  A.h = h;
+  A.n = n;
+  for (int r = 0; r < 2; ++r) {
+    bool on = r == 0 ? lower : upper;
+    RunPtrs& R = A.run[r];
+    R.pts = on ? (const int4*)(ws + pl.pts) : nullptr;
+    R.pv0 = (int*)(ws + pl.pv0[r]);
+    R.nx0 = (int*)(ws + pl.nx0[r]);
+    R.pv = (int*)(ws + pl.pv[r]);
+    R.nx = (int*)(ws + pl.nx[r]);
+    R.zs = r == 0 ? 1 : -1;
+    if (on)
+      hipLaunchKernelGGL(k_init_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0,
+                         (int*)(ws + pl.len[r][0]), n);
+  }
+  int buf = 0;
+  for (int k = 1; k <= levels; ++k) {
+    A.width = int64_t(1) << k;
+    A.half = A.width >> 1;
+    int64_t blocks = (n + A.width - 1) / A.width;
+    int64_t last_s = (blocks - 1) * A.width;
+    bool trailing = last_s + A.half >= n;
+    A.merges = trailing ? blocks - 1 : blocks;
+    for (int r = 0; r < 2; ++r) {
+      RunPtrs& R = A.run[r];
+      R.ev_in = (const Event*)(ws + pl.ev[r][buf]);
+      R.tau_in = (const double*)(ws + pl.tau[r][buf]);
+      R.len_in = (const int*)(ws + pl.len[r][buf]);
+      R.ev_out = (Event*)(ws + pl.ev[r][buf ^ 1]);
+      R.tau_out = (double*)(ws + pl.tau[r][buf ^ 1]);
+      R.len_out = (int*)(ws + pl.len[r][buf ^ 1]);
+      if (R.pts)
+        hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.pv,
+                           R.nx, n);
+    }
+    if (events) (void)hipEventRecord(events[2 * k], s);
+    if (A.merges > 0)
+      hipLaunchKernelGGL(k_merge_level, dim3(grid_for(2 * A.merges, int64_t(1) << 30)), dim3(256),
+                         0, s, A);
+    if (events) (void)hipEventRecord(events[2 * k + 1], s);
+    if (trailing)
+      hipLaunchKernelGGL(k_passthrough, dim3(grid_for(2 * (n - last_s), 1024), 2), dim3(256), 0,
+                         s, A, last_s);
+    HULL_LAUNCH_CHECK();
+    buf ^= 1;
+  }
+  *final_buf = buf;
+  return HULL_OK;
+}
+
+int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
+                  void* const* events, int32_t nevents) {
+  if (n < 0 || n > kMaxN || !d_info || (n > 0 && !d_xyz) || !d_faces || cap < 2 * n || !d_ws)
+    return HULL_EINVAL;
+  const int L = levels_for(n);
+  if (events && nevents < 2 * L + 3) return HULL_EINVAL;
+  hipEvent_t* ev = (hipEvent_t*)events;
+  Plan pl = make_plan(n);
+  if (ws_bytes < pl.total) return HULL_EWORKSPACE;
+  char* ws = (char*)d_ws;
+  Header* h = (Header*)(ws + pl.header);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  init_header(h, s);
+  if (n < 3) {
+    hipLaunchKernelGGL(k_info_small, dim3(1), dim3(64), 0, s, d_info, h);
+    HULL_LAUNCH_CHECK();
+    if (ev)
+      for (int q = 1; q < 2 * L + 3; ++q) (void)hipEventRecord(ev[q], s);
+    return HULL_OK;
+  }
+  int32_t rc = sort_points(d_xyz, n, ws, pl, s);
+  if (rc) return rc;
+  if (ev) (void)hipEventRecord(ev[1], s);
+  int buf = 0;
+  rc = run_levels(n, ws, pl, s, lower, upper, L, &buf, ev);
+  if (rc) return rc;
+  const Event* evL = lower ? (const Event*)(ws + pl.ev[0][buf]) : nullptr;
+  const Event* evU = upper ? (const Event*)(ws + pl.ev[1][buf]) : nullptr;
+  hipLaunchKernelGGL(k_extract, dim3(grid_for(2 * n, 2048)), dim3(256), 0, s, evL,
+                     (const int*)(ws + pl.len[0][buf]), evU, (const int*)(ws + pl.len[1][buf]),
+                     (const int4*)(ws + pl.pts), d_faces, cap, d_info, h);
+  if (ev) (void)hipEventRecord(ev[2 * L + 2], s);
+  HULL_LAUNCH_CHECK();
+  return HULL_OK;
+}
+
+int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,
+               int32_t* d_block_len, int32_t* d_order, int64_t* d_info, void* d_ws,
+               size_t ws_bytes, hipStream_t s) {
+  if (n < 1 || n > kMaxN || !d_xyz || !d_ev || !d_block_len || !d_order || !d_info || !d_ws ||
+      (run != 0 && run != 1))
+    return HULL_EINVAL;
+  Plan pl = make_plan(n);
+  if (ws_bytes < pl.total) return HULL_EWORKSPACE;
+  char* ws = (char*)d_ws;
+  Header* h = (Header*)(ws + pl.header);
+  init_header(h, s);
+  int32_t rc = sort_points(d_xyz, n, ws, pl, s);
+  if (rc) return rc;
+  int L = levels_for(n);
+  if (level >= 0 && level < L) L = level;
+  int buf = 0;
+  rc = run_levels(n, ws, pl, s, run == 0, run == 1, L, &buf, nullptr);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_export_movies, dim3(grid_for(2 * n, 1024)), dim3(256), 0, s,
+                     (const Event*)(ws + pl.ev[run][buf]), (const int*)(ws + pl.len[run][buf]),
+                     (const int4*)(ws + pl.pts), n, int64_t(1) << L, d_ev, d_block_len, d_order);
+  hipLaunchKernelGGL(k_info_small, dim3(1), dim3(64), 0, s, d_info, h);
+  HULL_LAUNCH_CHECK();
+  return HULL_OK;
+}
+
+}  // namespace hull
+
+extern "C" {
+
+const char* hull_strerror(int32_t code) {
+  switch (code) {
+    case HULL_OK: return "ok";
+    case HULL_EINVAL: return "invalid argument";
+    case HULL_EWORKSPACE: return "workspace too small";
+    case HULL_ERANGE: return "coordinate outside [-2^29, 2^29]";
+    case HULL_EHIP: return "HIP runtime error";
+    case HULL_EINTERNAL: return "internal consistency bound exceeded";
+    default: return "unknown status";
+  }
+}
+
+int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes) {
+  (void)flags;
+  if (!bytes || n < 0 || n > hull::kMaxN) return HULL_EINVAL;
+  *bytes = hull::make_plan(n).total;
+  return HULL_OK;
+}
+
+int32_t hull_lower(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                   void* d_ws, size_t ws_bytes, void* stream) {
+  return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
+                         false, nullptr, 0);
+}
+
+int32_t hull_full(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, void* stream) {
+  return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
+                         true, nullptr, 0);
+}
+
+int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
+                        int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream,
+                        void* const* events, int32_t nevents) {
+  if (!events) return HULL_EINVAL;
+  return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
+                         true, events, nevents);
+}
+
+int32_t hull_movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,
+                    int32_t* d_block_len, int32_t* d_order, int64_t* d_info, void* d_ws,
+                    size_t ws_bytes, void* stream) {
+  return hull::movies(d_xyz, n, run, level, d_ev, d_block_len, d_order, d_info, d_ws, ws_bytes,
+                      (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+"""Python binding of the C ABI in ``include/hull3d.h`` (ctypes).
+
+Argument marshalling only: every step of the hull runs in the HIP library.
+PyTorch supplies device memory and the current stream.  If the library has
+not been built, every call raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libhull3d.so")
+
+HULL_OK = 0
+HULL_EINVAL = -1
+HULL_EWORKSPACE = -2
+HULL_ERANGE = -3
+HULL_EHIP = -4
+HULL_EINTERNAL = -5
+
+_lib = None
+
+
+class HullError(RuntimeError):
+    def __init__(self, code, where=""):
+        msg = _strerror(code) if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+def _strerror(code):
+    return _lib.hull_strerror(code).decode()
+
+
+def lib():
+    """The loaded HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise RuntimeError(f"HIP library not built: {SO} (run __graft_entry__.build())")
+    L = ctypes.CDLL(SO)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    i32 = ctypes.c_int32
+    sz = ctypes.c_size_t
+    L.hull_strerror.argtypes = [i32]
+    L.hull_strerror.restype = ctypes.c_char_p
+    L.hull_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(sz)]
+    L.hull_workspace_bytes.restype = i32
+    for f in (L.hull_lower, L.hull_full):
+        f.argtypes = [P, i64, P, i64, P, P, sz, P]
+        f.restype = i32
+    L.hull_full_timed.argtypes = [P, i64, P, i64, P, P, sz, P, P, i32]
+    L.hull_full_timed.restype = i32
+    L.hull_movies.argtypes = [P, i64, i32, i32, P, P, P, P, P, sz, P]
+    L.hull_movies.restype = i32
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names declared in include/hull3d.h that the library exports."""
+    L = lib()
+    names = ["hull_strerror", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
+             "hull_movies"]
+    return [n for n in names if hasattr(L, n)]
+
+
+def workspace_bytes(n, flags=0):
+    out = ctypes.c_size_t(0)
+    rc = lib().hull_workspace_bytes(int(n), int(flags), ctypes.byref(out))
+    if rc:
+        raise HullError(rc, "hull_workspace_bytes")
+    return out.value
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_points(xyz):
+    import torch
+    if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.int32):
+        raise TypeError("points must be a CUDA int32 tensor")
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+        raise ValueError("points must be a contiguous [n, 3] tensor")
+
+
+class Workspace:
+    """Reusable device workspace (grows on demand)."""
+
+    def __init__(self, device=None):
+        self.buf = None
+        self.device = device
+
+    def get(self, nbytes, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+def hull(xyz, lower_only=False, ws=None, faces=None, info=None, stream=None):
+    """Faces (device int32 [cap, 3]) and info (device int64 [2]: status, F).
+
+    Asynchronous: the first info[1] rows of ``faces`` are valid once the
+    stream reaches this point.  Use :func:`hull_sync` for a checked result."""
+    import torch
+    _check_points(xyz)
+    n = xyz.shape[0]
+    dev = xyz.device
+    cap = max(2 * n, 1)
+    if faces is None:
+        faces = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+    if info is None:
+        info = torch.empty(2, dtype=torch.int64, device=dev)
+    nb = workspace_bytes(n)
+    wbuf = (ws or Workspace()).get(nb, dev)
+    fn = lib().hull_lower if lower_only else lib().hull_full
+    rc = fn(ctypes.c_void_p(xyz.data_ptr()), n, ctypes.c_void_p(faces.data_ptr()), faces.shape[0],
+            ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(),
+            _stream(stream))
+    if rc:
+        raise HullError(rc, "hull_lower" if lower_only else "hull_full")
+    return faces, info
+
+
+def hull_sync(xyz, lower_only=False, ws=None):
+    """Blocking call: the face tensor [F, 3] on the device (checked status)."""
+    faces, info = hull(xyz, lower_only=lower_only, ws=ws)
+    st, F = (int(v) for v in info.cpu())
+    if st:
+        raise HullError(st, "device")
+    return faces[:F]
+
+
+def movies(xyz, run, level, ws=None):
+    """Movies after ``level`` merge levels: (events [E, 4] in rank terms,
+    per-block lengths, rank -> input index), all copied to the host."""
+    import torch
+    _check_points(xyz)
+    n = xyz.shape[0]
+    dev = xyz.device
+    ev = torch.zeros((2 * n, 4), dtype=torch.int32, device=dev)
+    bl = torch.zeros(n, dtype=torch.int32, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    info = torch.empty(2, dtype=torch.int64, device=dev)
+    nb = workspace_bytes(n)
+    wbuf = (ws or Workspace()).get(nb, dev)
+    rc = lib().hull_movies(ctypes.c_void_p(xyz.data_ptr()), n, int(run), int(level),
+                           ctypes.c_void_p(ev.data_ptr()), ctypes.c_void_p(bl.data_ptr()),
+                           ctypes.c_void_p(order.data_ptr()), ctypes.c_void_p(info.data_ptr()),
+                           ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(), _stream(None))
+    if rc:
+        raise HullError(rc, "hull_movies")
+    st = int(info[0].item())
+    if st:
+        raise HullError(st, "device")
+    return ev.cpu().numpy(), bl.cpu().numpy(), order.cpu().numpy()

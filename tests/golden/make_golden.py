@@ -1,0 +1,82 @@
+"""Writes the stored expected values for the full-size parity tests.
+
+Calls only the oracle (``oracle/``) and the seeded input generators: for each
+workload it records the oracle's face count, vertex count, the SHA-256 of its
+canonical face array (oracle.validate.canonical, int32 little-endian) for the
+full hull and for the lower hull, and the oracle's per-level counters of the
+bottom-up driver (events read, events written, points touched, merges) that
+define the algorithmic bytes of each merge level.
+
+usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3
+(the lower and upper runs go to two processes)
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from oracle import validate  # noqa: E402
+from paper_1205_1171_amd import workloads  # noqa: E402
+
+MAKERS = {
+    "cfg1": workloads.cfg1,
+    "cfg2_sphere": workloads.cfg2_sphere,
+    "cfg2_ball": workloads.cfg2_ball,
+    "cfg3": workloads.cfg3,
+}
+
+
+def digest(faces):
+    c = validate.canonical(faces).astype("<i4")
+    return hashlib.sha256(c.tobytes()).hexdigest()
+
+
+def _run(args):
+    name, which = args
+    p = MAKERS[name]()
+    t = time.time()
+    f, st = oracle.hull(p, lower_only=which == 0, upper_only=which == 1, stats=True)
+    return which, f, st[which], time.time() - t
+
+
+def make(name):
+    p = MAKERS[name]()
+    with ProcessPoolExecutor(2) as ex:
+        res = sorted(ex.map(_run, [(name, 0), (name, 1)]), key=lambda r: r[0])
+    lower, upper = res[0][1], res[1][1]
+    faces = np.concatenate([lower, upper])
+    rec = {
+        "config": name,
+        "n": int(len(p)),
+        "input_sha256": hashlib.sha256(np.ascontiguousarray(p, dtype="<i4").tobytes()).hexdigest(),
+        "F": int(len(faces)),
+        "F_lower": int(len(lower)),
+        "V": int(validate.vertex_count(faces)),
+        "euler_ok": bool(validate.euler_ok(faces)),
+        "manifold_ok": bool(validate.manifold_ok(faces)),
+        "sha256_full": digest(faces),
+        "sha256_lower": digest(lower),
+        "level_stats_columns": ["events_in", "events_out", "points_touched", "merges"],
+        "level_stats_lower": res[0][2].tolist(),
+        "level_stats_upper": res[1][2].tolist(),
+        "oracle_seconds_lower": res[0][3],
+        "oracle_seconds_upper": res[1][3],
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(name, rec["F"], rec["V"], rec["oracle_seconds_lower"], rec["oracle_seconds_upper"],
+          flush=True)
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:]:
+        make(name)

@@ -1,0 +1,72 @@
+"""The C ABI on the host: every function declared in include/hull3d.h is
+exported by the built library, and argument errors are reported
+synchronously without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1205_1171_amd import hull
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(hull.SO):
+        from paper_1205_1171_amd import build
+        build.build()
+    return hull.lib()
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hull_[A-Za-z0-9_]+)\s*\(",
+                                src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert "hull_full" in names and "hull_lower" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror(L):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.hull_strerror(code)
+    assert b"unknown" in L.hull_strerror(77)
+
+
+def test_workspace_bytes(L):
+    assert hull.workspace_bytes(0) > 0
+    a, b = hull.workspace_bytes(1000), hull.workspace_bytes(100000)
+    assert b > a
+    out = ctypes.c_size_t(0)
+    assert L.hull_workspace_bytes(-1, 0, ctypes.byref(out)) == hull.HULL_EINVAL
+    assert L.hull_workspace_bytes((1 << 26) + 1, 0, ctypes.byref(out)) == hull.HULL_EINVAL
+    assert L.hull_workspace_bytes(10, 0, None) == hull.HULL_EINVAL
+
+
+def test_argument_errors_are_synchronous(L):
+    P = ctypes.c_void_p
+    fake = P(0x1000)  # never dereferenced: every call below fails its checks first
+    info = P(0x2000)
+    ws = hull.workspace_bytes(100)
+    for fn in (L.hull_lower, L.hull_full):
+        assert fn(None, 100, fake, 200, info, fake, ws, None) == hull.HULL_EINVAL
+        assert fn(fake, -1, fake, 200, info, fake, ws, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 199, info, fake, ws, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, None, 200, info, fake, ws, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 200, None, fake, ws, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 200, info, None, ws, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 200, info, fake, ws - 1, None) == hull.HULL_EWORKSPACE
+        assert fn(fake, (1 << 26) + 1, fake, 1 << 28, info, fake, 1 << 40, None) == hull.HULL_EINVAL
+    assert L.hull_movies(fake, 100, 2, 1, fake, fake, fake, info, fake, ws, None) == hull.HULL_EINVAL
+    assert L.hull_movies(fake, 0, 0, 1, fake, fake, fake, info, fake, ws, None) == hull.HULL_EINVAL

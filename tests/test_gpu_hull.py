@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+The bar is bit-exact: the canonical face set (every face rotated to start at
+its smallest input index, orientation kept, rows sorted) must equal the
+oracle's, and so must every intermediate movie (events in rank terms, in
+order, with their kind).  Full-size workloads compare against digests that
+tests/golden/make_golden.py wrote from the oracle alone.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import validate
+from paper_1205_1171_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1205_1171_amd import hull
+    assert torch.cuda.is_available()
+    hull.lib()
+    return hull
+
+
+@pytest.fixture(scope="module")
+def ws(H):
+    return H.Workspace()
+
+
+def gpu_faces(H, ws, p, lower_only=False):
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(p, dtype=np.int32)).cuda()
+    f = H.hull_sync(x, lower_only=lower_only, ws=ws)
+    return f.cpu().numpy()
+
+
+def same(a, b):
+    a, b = validate.canonical(a), validate.canonical(b)
+    return a.shape == b.shape and bool((a == b).all())
+
+
+def test_cfg1_bit_exact(H, ws):
+    p = workloads.cfg1()
+    say("cfg1 n=4096 full")
+    g = gpu_faces(H, ws, p)
+    assert same(g, oracle.hull(p))
+    say("cfg1 n=4096 lower")
+    gl = gpu_faces(H, ws, p, lower_only=True)
+    assert same(gl, oracle.hull(p, lower_only=True))
+    rec = json.load(open(os.path.join(GOLDEN, "cfg1.json")))
+    assert hashlib.sha256(validate.canonical(g).astype("<i4").tobytes()).hexdigest() == rec["sha256_full"]
+
+
+def test_small_n(H, ws):
+    for n in (0, 1, 2):
+        say("small n", n)
+        assert gpu_faces(H, ws, np.arange(3 * n, dtype=np.int32).reshape(n, 3)).shape == (0, 3)
+    tri = np.array([[0, 0, 0], [5, 0, 1], [0, 7, 2]], dtype=np.int32)
+    say("triangle")
+    assert same(gpu_faces(H, ws, tri), [[0, 1, 2], [0, 2, 1]])
+
+
+def _cases(rng, count):
+    for t in range(count):
+        n = int(rng.integers(3, 260))
+        kind = t % 9
+        if kind == 0:
+            p = workloads.lattice(rng, n, 1)
+        elif kind == 1:
+            p = workloads.lattice(rng, n, 3)
+        elif kind == 2:
+            p = workloads.lattice(rng, n, 7)
+        elif kind == 3:
+            p = workloads.lattice(rng, n, 5)
+            p[:, 0] = 4
+        elif kind == 4:
+            p = workloads.lattice(rng, n, 5)
+            p[:, 2] = 0
+        elif kind == 5:
+            q = workloads.lattice(rng, max(n // 4, 1), 6)
+            p = q[rng.integers(0, len(q), size=n)]
+        elif kind == 6:
+            p = workloads.sphere(rng, n, 1 << 10)
+        elif kind == 7:
+            p = workloads.gaussian(rng, n, sigma=8, clip=1 << 20)
+        else:
+            p = workloads.cube(rng, n, 1 << 29)  # the coordinate bound itself
+        yield t, p
+
+
+def test_degenerate_and_random_small(H, ws):
+    rng = np.random.default_rng(7)
+    for t, p in _cases(rng, 270):
+        say("case", t, "n", len(p))
+        assert same(gpu_faces(H, ws, p), oracle.hull(p)), t
+
+
+@pytest.mark.parametrize("n", [4, 5, 7, 31, 33, 100, 1000, 1025, 4097, 6000])
+def test_ragged_sizes(H, ws, n):
+    rng = np.random.default_rng(n)
+    p = workloads.cube(rng, n, 1 << 20) if n % 2 else workloads.lattice(rng, n, 40)
+    say("ragged n", n)
+    assert same(gpu_faces(H, ws, p), oracle.hull(p))
+    assert same(gpu_faces(H, ws, p, lower_only=True), oracle.hull(p, lower_only=True))
+
+
+def test_movies_every_level(H, ws):
+    import torch
+    rng = np.random.default_rng(3)
+    for t, n, kind in ((0, 300, "lattice"), (1, 777, "gauss"), (2, 1024, "sphere"), (3, 100, "flatx")):
+        if kind == "lattice":
+            p = workloads.lattice(rng, n, 6)
+        elif kind == "gauss":
+            p = workloads.gaussian(rng, n, sigma=4, clip=1 << 20)
+        elif kind == "sphere":
+            p = workloads.sphere(rng, n, 1 << 12)
+        else:
+            p = workloads.lattice(rng, n, 9)
+            p[:, 0] = 1
+        x = torch.from_numpy(p).cuda()
+        order = oracle.sort_order(p)
+        for run in (0, 1):
+            for level in range(1, oracle.levels_for(n) + 1):
+                say("movies", kind, "run", run, "level", level)
+                ev, bl, gorder = H.movies(x, run, level, ws=ws)
+                assert (gorder == order).all()
+                want, wbl = oracle.level_movies(p, run, level)
+                w = 1 << level
+                pos = 0
+                for b, s in enumerate(range(0, n, w)):
+                    got = ev[2 * s: 2 * s + bl[s]]
+                    assert bl[s] == wbl[b], (run, level, s)
+                    assert (got == want[pos: pos + wbl[b]]).all(), (run, level, s)
+                    pos += wbl[b]
+
+
+def test_range_error_reported_on_device(H, ws):
+    import torch
+    p = workloads.cube(np.random.default_rng(1), 1000, 1 << 20)
+    p[517, 1] = (1 << 29) + 1
+    x = torch.from_numpy(p).cuda()
+    say("range error")
+    faces, info = H.hull(x, ws=ws)
+    st, F = (int(v) for v in info.cpu())
+    assert st == H.HULL_ERANGE and F == 0
+    p[517, 1] = -(1 << 29)
+    say("range edge")
+    assert same(gpu_faces(H, ws, p), oracle.hull(p))
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle digest for {name}")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
+def test_full_size_digest(H, ws, name):
+    rec = _golden(name)
+    p = getattr(workloads, name)()
+    assert len(p) == rec["n"]
+    assert hashlib.sha256(np.ascontiguousarray(p, dtype="<i4").tobytes()).hexdigest() == rec["input_sha256"]
+    say("full size", name, "lower")
+    gl = gpu_faces(H, ws, p, lower_only=True)
+    assert len(gl) == rec["F_lower"]
+    assert hashlib.sha256(validate.canonical(gl).astype("<i4").tobytes()).hexdigest() == rec["sha256_lower"]
+    say("full size", name, "full")
+    g = gpu_faces(H, ws, p)
+    assert len(g) == rec["F"]
+    assert hashlib.sha256(validate.canonical(g).astype("<i4").tobytes()).hexdigest() == rec["sha256_full"]
+    assert validate.euler_ok(g) and validate.manifold_ok(g)
