@@ -1,0 +1,127 @@
+// Events of a movie as comparison candidates, and their exact order.
+#pragma once
+#include "common.hpp"
+#include "predicates.hpp"
+
+namespace hull {
+
+struct Cand {
+  Tri t;
+  double st;  // standard part of tau (NaN: not covered by the fast path)
+  int kind;   // 1 insertion, 0 deletion
+};
+
+// Pointers of one run (lower or upper) for the lane-serial merge strategy.
+struct RunPtrs {
+  const int4* pts;
+  int* pv0;
+  int* nx0;
+  int* pv;
+  int* nx;
+  const Event* ev_in;
+  const double* tau_in;
+  const int* len_in;
+  Event* ev_out;
+  double* tau_out;
+  int* len_out;
+  int zs;
+};
+
+struct LevelArgs {
+  RunPtrs run[2];
+  Header* h;
+  int64_t n;
+  int64_t half;   // size of a left block
+  int64_t width;  // size of a merged block
+  int64_t merges; // merges per run
+};
+
+// Exact (time, rank triple) order of two distinct-or-equal events.
+__device__ __noinline__ int ev_cmp_exact(const int4* pts, const Cand& A, const Cand& B, int zs) {
+  Coef ca, cb;
+  coef_of(pts[A.t.a], pts[A.t.w], pts[A.t.b], zs, ca);
+  coef_of(pts[B.t.a], pts[B.t.w], pts[B.t.b], zs, cb);
+  int s = tau_cmp_exact(ca, cb);
+  if (s) return s;
+  if (A.t.a != B.t.a) return A.t.a < B.t.a ? -1 : 1;
+  if (A.t.w != B.t.w) return A.t.w < B.t.w ? -1 : 1;
+  if (A.t.b != B.t.b) return A.t.b < B.t.b ? -1 : 1;
+  return 0;
+}
+
+__device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand& B, int zs) {
+  if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
+  int s = std_cmp(A.st, B.st);
+  if (s) return s;
+  return ev_cmp_exact(pts, A, B, zs);
+}
+
+// Perturbed sign of D(a, b, c) (xy orientation).
+__device__ __forceinline__ int d_sign(int4 P, int4 Q, int4 R) {
+  int64_t D0 = ((int64_t)Q.x - P.x) * ((int64_t)R.y - P.y) -
+               ((int64_t)R.x - P.x) * ((int64_t)Q.y - P.y);
+  if (D0) return D0 > 0 ? 1 : -1;
+  Coef c;
+  coef_of(P, Q, R, 1, c);
+  return c.dsign;
+}
+
+__device__ __forceinline__ Cand make_cand(const int4* pts, int a, int w, int b, int4 A, int4 W,
+                                          int4 B, int kind, int zs) {
+  Cand c;
+  c.t = Tri{a, w, b};
+  c.kind = kind;
+  c.st = tau_std(A, W, B, zs);
+  return c;
+}
+
+__device__ __forceinline__ Cand cand_of(const Event* ev, const double* tau, int64_t q) {
+  Event E = ev[q];
+  Cand c;
+  c.t = Tri{E.a, E.w, E.b};
+  c.kind = E.kind;
+  c.st = tau[q];
+  return c;
+}
+
+// Pointers of one run for the parallel (bridge walk and scatter) strategy.
+struct ParRun {
+  const int4* pts;
+  int* pv0;
+  int* nx0;
+  const Event* ev_in;
+  const double* tau_in;
+  const int* len_in;
+  Event* ev_out;
+  double* tau_out;
+  int* len_out;
+  int* cntR;  // per point: # child events changing nx(p)
+  int* cntL;  // per point: # child events changing pv(p)
+  int* offR;
+  int* offL;
+  int* curR;
+  int* curL;
+  int* entR;  // event slots, grouped by point, time-sorted
+  int* entL;
+  Event* bev;  // bridge events of merge s at [2s, 2s + nB[s])
+  double* btau;
+  int2* buv;   // (u, v) after each bridge event
+  int* nB;     // at merge start s
+  int2* uv0;   // (u0, v0): the bridge at -inf, at merge start s
+  int* surv;   // per input slot: survives into the merged movie (2n + 1)
+  int* jb;     // per input slot: # bridge events before it
+  int* pre;    // exclusive scan of surv (2n + 1)
+  int zs;
+};
+
+struct ParLevel {
+  ParRun run[2];
+  Header* h;
+  int64_t n;
+  int k;           // level: input blocks of 2^(k-1) points, merged blocks of 2^k
+  int64_t merges;  // merges per run (an unpaired trailing block is not one)
+};
+
+int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s);
+
+}  // namespace hull

@@ -23,81 +23,14 @@
 //      output, every child event updates its child's chain, bridge moves are
 //      output events of the merged chain;
 //   3. splice the -inf chains at the -inf bridge.
+#include <stdlib.h>
+
 #include <algorithm>
 
 #include "common.hpp"
-#include "predicates.hpp"
+#include "events.hpp"
 
 namespace hull {
-
-struct Cand {
-  Tri t;
-  double st;  // standard part of tau (NaN: not covered by the fast path)
-  int kind;   // 1 insertion, 0 deletion
-};
-
-struct RunPtrs {
-  const int4* pts;
-  int* pv0;
-  int* nx0;
-  int* pv;
-  int* nx;
-  const Event* ev_in;
-  const double* tau_in;
-  const int* len_in;
-  Event* ev_out;
-  double* tau_out;
-  int* len_out;
-  int zs;
-};
-
-struct LevelArgs {
-  RunPtrs run[2];
-  Header* h;
-  int64_t n;
-  int64_t half;   // size of a left block
-  int64_t width;  // size of a merged block
-  int64_t merges; // merges per run
-};
-
-// Exact (time, rank triple) order of two distinct-or-equal events.
-__device__ __noinline__ int ev_cmp_exact(const int4* pts, const Cand& A, const Cand& B, int zs) {
-  Coef ca, cb;
-  coef_of(pts[A.t.a], pts[A.t.w], pts[A.t.b], zs, ca);
-  coef_of(pts[B.t.a], pts[B.t.w], pts[B.t.b], zs, cb);
-  int s = tau_cmp_exact(ca, cb);
-  if (s) return s;
-  if (A.t.a != B.t.a) return A.t.a < B.t.a ? -1 : 1;
-  if (A.t.w != B.t.w) return A.t.w < B.t.w ? -1 : 1;
-  if (A.t.b != B.t.b) return A.t.b < B.t.b ? -1 : 1;
-  return 0;
-}
-
-__device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand& B, int zs) {
-  if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
-  int s = std_cmp(A.st, B.st);
-  if (s) return s;
-  return ev_cmp_exact(pts, A, B, zs);
-}
-
-// Perturbed sign of D(a, b, c) (xy orientation).
-__device__ __forceinline__ int d_sign(int4 P, int4 Q, int4 R) {
-  int64_t D0 = ((int64_t)Q.x - P.x) * ((int64_t)R.y - P.y) -
-               ((int64_t)R.x - P.x) * ((int64_t)Q.y - P.y);
-  if (D0) return D0 > 0 ? 1 : -1;
-  Coef c;
-  coef_of(P, Q, R, 1, c);
-  return c.dsign;
-}
-
-__device__ __forceinline__ Cand make_cand(const int4* pts, int a, int w, int b, int4 A, int4 W,
-                                          int4 B, int kind, int zs) {
-  Cand c;
-  c.t = Tri{a, w, b};
-  c.kind = kind;
-  c.st = tau_std(A, W, B, zs);
-  return c;
-}
 
 __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int64_t e) {
   const int4* pts = R.pts;
@@ -105,6 +38,11 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   int* nx = R.nx;
   const int zs = R.zs;
   const int nL = R.len_in[s], nR = R.len_in[m];
+  if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m)) {
+    atomicCAS(&h->err, 0, HULL_EINTERNAL);
+    R.len_out[s] = 0;
+    return;
+  }
   const Event* Lev = R.ev_in + 2 * s;
   const Event* Rev = R.ev_in + 2 * m;
   const double* Ltau = R.tau_in + 2 * s;
@@ -232,13 +170,18 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
 }
 
 __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
-  if (A.h->err) return;
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= 2 * A.merges) return;
   int r = g >= A.merges ? 1 : 0;
   int64_t q = g - r * A.merges;
   if (!A.run[r].pts) return;
   int64_t s = q * A.width, m = s + A.half, e = std::min(s + A.width, A.n);
+  // After an error the movies are empty, so that every later kernel still
+  // reads lengths that were written.
+  if (A.h->err) {
+    A.run[r].len_out[s] = 0;
+    return;
+  }
   merge_one(A.run[r], A.h, s, m, e);
 }
 
@@ -248,6 +191,7 @@ __global__ void __launch_bounds__(256) k_passthrough(LevelArgs A, int64_t s) {
   const RunPtrs& R = A.run[r];
   if (!R.pts) return;
   int len = R.len_in[s];
+  if (A.h->err || len < 0 || len > 2 * (A.n - s)) len = 0;
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < len;
        q += (int64_t)gridDim.x * blockDim.x) {
     R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
@@ -313,15 +257,18 @@ __global__ void k_info_small(int64_t* info, const Header* h) {
 __global__ void __launch_bounds__(256)
     k_export_movies(const Event* __restrict__ ev, const int* __restrict__ len,
                     const int4* __restrict__ pts, int64_t n, int64_t width, int32_t* d_ev,
-                    int32_t* d_block_len, int32_t* d_order) {
+                    int32_t* d_block_len, int32_t* d_order, const Header* h) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     d_order[p] = pts[p].w;
     bool start = p % width == 0;
-    d_block_len[p] = start ? len[p] : 0;
+    int L = start && !h->err ? len[p] : 0;
+    if (L < 0 || L > 2 * std::min(width, n - p)) L = 0;
+    d_block_len[p] = L;
   }
   for (int64_t s = 0; s < n; s += width) {
-    int L = len[s];
+    int L = h->err ? 0 : len[s];
+    if (L < 0 || L > 2 * std::min(width, n - s)) L = 0;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L;
          q += (int64_t)gridDim.x * blockDim.x) {
       Event E = ev[2 * s + q];
@@ -348,12 +295,27 @@ static unsigned grid_for(int64_t work, int64_t cap_blocks = 4096) {
 
 // Runs `levels` merge levels of the selected runs; returns the buffer index
 // holding the final movies.
+// Highest level merged by the lane-serial strategy; higher levels use the
+// parallel strategy.  Tunable through HULL_SERIAL_LEVELS (0 = parallel from
+// the first level, a large value = lane-serial throughout).
+static int serial_levels() {
+  const char* e = getenv("HULL_SERIAL_LEVELS");
+  if (e && *e) return atoi(e);
+  return 6;
+}
+
+// Runs `levels` merge levels of the selected runs; returns the buffer index
+// holding the final movies.
 static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bool lower,
                           bool upper, int levels, int* final_buf, hipEvent_t* events) {
   Header* h = (Header*)(ws + pl.header);
+  const int serial_max = serial_levels();
   LevelArgs A{};
   A.h = h;
   A.n = n;
+  ParLevel P{};
+  P.h = h;
+  P.n = n;
   for (int r = 0; r < 2; ++r) {
     bool on = r == 0 ? lower : upper;
     RunPtrs& R = A.run[r];
@@ -363,10 +325,32 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     R.pv = (int*)(ws + pl.pv[r]);
     R.nx = (int*)(ws + pl.nx[r]);
     R.zs = r == 0 ? 1 : -1;
+    ParRun& Q = P.run[r];
+    Q.pts = R.pts;
+    Q.pv0 = R.pv0;
+    Q.nx0 = R.nx0;
+    Q.zs = R.zs;
+    Q.cntR = (int*)(ws + pl.cntR[r]);
+    Q.cntL = (int*)(ws + pl.cntL[r]);
+    Q.offR = (int*)(ws + pl.offR[r]);
+    Q.offL = (int*)(ws + pl.offL[r]);
+    Q.curR = (int*)(ws + pl.curR[r]);
+    Q.curL = (int*)(ws + pl.curL[r]);
+    Q.entR = (int*)(ws + pl.entR[r]);
+    Q.entL = (int*)(ws + pl.entL[r]);
+    Q.bev = (Event*)(ws + pl.bev[r]);
+    Q.btau = (double*)(ws + pl.btau[r]);
+    Q.buv = (int2*)(ws + pl.buv[r]);
+    Q.nB = (int*)(ws + pl.nB[r]);
+    Q.uv0 = (int2*)(ws + pl.uv0[r]);
+    Q.surv = (int*)(ws + pl.surv[r]);
+    Q.jb = (int*)(ws + pl.jb[r]);
+    Q.pre = (int*)(ws + pl.pre[r]);
     if (on)
       hipLaunchKernelGGL(k_init_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0,
                          (int*)(ws + pl.len[r][0]), n);
   }
+  int32_t* partials = (int32_t*)(ws + pl.partials);
   int buf = 0;
   for (int k = 1; k <= levels; ++k) {
     A.width = int64_t(1) << k;
@@ -375,6 +359,7 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     int64_t last_s = (blocks - 1) * A.width;
     bool trailing = last_s + A.half >= n;
     A.merges = trailing ? blocks - 1 : blocks;
+    const bool serial = k <= serial_max;
     for (int r = 0; r < 2; ++r) {
       RunPtrs& R = A.run[r];
       R.ev_in = (const Event*)(ws + pl.ev[r][buf]);
@@ -383,14 +368,29 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
       R.ev_out = (Event*)(ws + pl.ev[r][buf ^ 1]);
       R.tau_out = (double*)(ws + pl.tau[r][buf ^ 1]);
       R.len_out = (int*)(ws + pl.len[r][buf ^ 1]);
-      if (R.pts)
+      ParRun& Q = P.run[r];
+      Q.ev_in = R.ev_in;
+      Q.tau_in = R.tau_in;
+      Q.len_in = R.len_in;
+      Q.ev_out = R.ev_out;
+      Q.tau_out = R.tau_out;
+      Q.len_out = R.len_out;
+      if (R.pts && serial)
         hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.pv,
                            R.nx, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
-    if (A.merges > 0)
-      hipLaunchKernelGGL(k_merge_level, dim3(grid_for(2 * A.merges, int64_t(1) << 30)), dim3(256),
-                         0, s, A);
+    if (A.merges > 0) {
+      if (serial) {
+        hipLaunchKernelGGL(k_merge_level, dim3(grid_for(2 * A.merges, int64_t(1) << 30), 1),
+                           dim3(256), 0, s, A);
+      } else {
+        P.k = k;
+        P.merges = A.merges;
+        int32_t rc = parallel_level(P, partials, s);
+        if (rc) return rc;
+      }
+    }
     if (events) (void)hipEventRecord(events[2 * k + 1], s);
     if (trailing)
       hipLaunchKernelGGL(k_passthrough, dim3(grid_for(2 * (n - last_s), 1024), 2), dim3(256), 0,
@@ -459,7 +459,8 @@ int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int3
   if (rc) return rc;
   hipLaunchKernelGGL(k_export_movies, dim3(grid_for(2 * n, 1024)), dim3(256), 0, s,
                      (const Event*)(ws + pl.ev[run][buf]), (const int*)(ws + pl.len[run][buf]),
-                     (const int4*)(ws + pl.pts), n, int64_t(1) << L, d_ev, d_block_len, d_order);
+                     (const int4*)(ws + pl.pts), n, int64_t(1) << L, d_ev, d_block_len, d_order,
+                     h);
   hipLaunchKernelGGL(k_info_small, dim3(1), dim3(64), 0, s, d_info, h);
   HULL_LAUNCH_CHECK();
   return HULL_OK;

@@ -1,0 +1,413 @@
+// Parallel merge strategy for large blocks: the kinetic merge of two movies
+// (Sec. 2, the merge step) with only the bridge walk left serial.
+//
+// In the merge of L and R, a child event matters to the bridge only when it
+// changes a link of a current bridge endpoint (nx(u), pv(u), pv(v), nx(v));
+// every other child event just passes through or is hidden, depending on
+// where the bridge was at its time.  So:
+//   1. per-point lists of the child events that change the point's links,
+//      in time order (a counting sort by point, then a sort of each short
+//      list by event position: a movie is already in time order);
+//   2. the bridge walk, one thread per merge: the four bridge moves and the
+//      next link change of u and v, earliest first.  Its length is the number
+//      of bridge events plus the link changes of the endpoints, not the size
+//      of the movies;
+//   3. each child event finds, by binary search over the bridge events, the
+//      bridge at its time: an L event survives when its point is left of u,
+//      an R event when right of v;
+//   4. the merged movie is the three time-sorted lists (L survivors, R
+//      survivors, bridge events) merged: every element's position is its
+//      rank in its own list plus its rank in the two others (prefix sums and
+//      binary searches).
+// The result is the same movie as the lane-serial merge, event for event.
+#include <algorithm>
+
+#include "common.hpp"
+#include "events.hpp"
+
+namespace hull {
+
+__device__ __forceinline__ int64_t in_block_start(int64_t q, int k) {
+  return ((q >> 1) >> (k - 1)) << (k - 1);
+}
+
+// # of events among slots [base, base + len) strictly before X.
+__device__ int count_before(const int4* pts, const Event* ev, const double* tau, int64_t base,
+                            int len, const Cand& X, int zs) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    Cand c = cand_of(ev, tau, base + mid);
+    if (ev_cmp(pts, c, X, zs) < 0) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) k_par_zero(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    R.cntR[p] = 0;
+    R.cntL[p] = 0;
+    R.curR[p] = 0;
+    R.curL[p] = 0;
+  }
+}
+
+// Which links an event changes: nx(a) and pv(b); an insertion also sets
+// nx(w) and pv(w).
+__global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts || P.h->err) return;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * P.n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t sb = in_block_start(q, P.k);
+    if (q - 2 * sb >= R.len_in[sb]) continue;
+    Event E = R.ev_in[q];
+    atomicAdd(&R.cntR[E.a], 1);
+    atomicAdd(&R.cntL[E.b], 1);
+    if (E.kind) {
+      atomicAdd(&R.cntR[E.w], 1);
+      atomicAdd(&R.cntL[E.w], 1);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts || P.h->err) return;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * P.n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t sb = in_block_start(q, P.k);
+    if (q - 2 * sb >= R.len_in[sb]) continue;
+    Event E = R.ev_in[q];
+    R.entR[R.offR[E.a] + atomicAdd(&R.curR[E.a], 1)] = (int)q;
+    R.entL[R.offL[E.b] + atomicAdd(&R.curL[E.b], 1)] = (int)q;
+    if (E.kind) {
+      R.entR[R.offR[E.w] + atomicAdd(&R.curR[E.w], 1)] = (int)q;
+      R.entL[R.offL[E.w] + atomicAdd(&R.curL[E.w], 1)] = (int)q;
+    }
+  }
+}
+
+__device__ void sort_slots(int* a, int k) {
+  if (k <= 24) {
+    for (int i = 1; i < k; ++i) {
+      int x = a[i], j = i - 1;
+      while (j >= 0 && a[j] > x) {
+        a[j + 1] = a[j];
+        --j;
+      }
+      a[j + 1] = x;
+    }
+    return;
+  }
+  int gap = 1;
+  while (gap < k / 3) gap = 3 * gap + 1;
+  for (; gap > 0; gap /= 3)
+    for (int i = gap; i < k; ++i) {
+      int x = a[i], j = i;
+      while (j >= gap && a[j - gap] > x) {
+        a[j] = a[j - gap];
+        j -= gap;
+      }
+      a[j] = x;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts || P.h->err) return;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    sort_slots(R.entR + R.offR[p], R.cntR[p]);
+    sort_slots(R.entL + R.offL[p], R.cntL[p]);
+  }
+}
+
+// Link of p after an event that changes it.
+__device__ __forceinline__ int right_after(const Event& E, int p) {
+  return p == E.a ? (E.kind ? E.w : E.b) : E.b;
+}
+__device__ __forceinline__ int left_after(const Event& E, int p) {
+  return p == E.b ? (E.kind ? E.w : E.a) : E.a;
+}
+
+// Position in a point's list of its first change strictly after T.
+__device__ int first_after(const ParRun& R, const int* ent, int off, int cnt, bool haveT,
+                           const Cand& T) {
+  if (!haveT) return 0;
+  int lo = 0, hi = cnt;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    Cand c = cand_of(R.ev_in, R.tau_in, ent[off + mid]);
+    if (ev_cmp(R.pts, c, T, R.zs) > 0) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+struct Endpoint {
+  int p;      // the point
+  int nx, pv; // its links at the current time
+  int cr, cl; // next unprocessed change in its right / left list
+};
+
+__device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) {
+  int p = X.p;
+  int oR = R.offR[p], nR = R.cntR[p], oL = R.offL[p], nL = R.cntL[p];
+  X.cr = first_after(R, R.entR, oR, nR, haveT, T);
+  X.cl = first_after(R, R.entL, oL, nL, haveT, T);
+  X.nx = X.cr > 0 ? right_after(R.ev_in[R.entR[oR + X.cr - 1]], p) : R.nx0[p];
+  X.pv = X.cl > 0 ? left_after(R.ev_in[R.entL[oL + X.cl - 1]], p) : R.pv0[p];
+}
+
+__device__ void walk_one(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e) {
+  const int4* pts = R.pts;
+  const int zs = R.zs;
+  // bridge at t = -inf
+  int u = (int)m - 1, v = (int)m;
+  int4 Pu = pts[u], Pv = pts[v];
+  for (int guard = 0;; ++guard) {
+    if (guard > 2 * (e - s) + 4) {
+      atomicCAS(&h->err, 0, HULL_EINTERNAL);
+      R.nB[s] = 0;
+      return;
+    }
+    int w = R.nx0[v];
+    if (w != kNil) {
+      int4 Pw = pts[w];
+      if (d_sign(Pu, Pv, Pw) < 0) {
+        v = w;
+        Pv = Pw;
+        continue;
+      }
+    }
+    w = R.pv0[u];
+    if (w != kNil) {
+      int4 Pw = pts[w];
+      if (d_sign(Pw, Pu, Pv) < 0) {
+        u = w;
+        Pu = Pw;
+        continue;
+      }
+    }
+    break;
+  }
+  const int u0 = u, v0 = v;
+  R.uv0[s] = make_int2(u0, v0);
+
+  bool haveT = false;
+  Cand T;
+  T.t = Tri{-1, -1, -1};
+  T.st = 0.0;
+  T.kind = 0;
+  Endpoint U{u, 0, 0, 0, 0}, V{v, 0, 0, 0, 0};
+  lookup(R, U, haveT, T);
+  lookup(R, V, haveT, T);
+  int nb = 0;
+  const int64_t cap = 2 * (e - s);
+  const int64_t iter_cap = (int64_t)R.len_in[s] + R.len_in[m] + 4 * (e - s) + 16;
+  Event* bout = R.bev + 2 * s;
+  double* btau = R.btau + 2 * s;
+  int2* buv = R.buv + 2 * s;
+  for (int64_t it = 0;; ++it) {
+    if (it > iter_cap) {
+      atomicCAS(&h->err, 0, HULL_EINTERNAL);
+      break;
+    }
+    // candidates: 0..3 bridge moves, 4..7 next link changes of u and v
+    Cand c[8];
+    bool ok[8];
+    ok[0] = U.nx != kNil;
+    ok[1] = U.pv != kNil;
+    ok[2] = V.pv != kNil;
+    ok[3] = V.nx != kNil;
+    if (ok[0]) c[0] = make_cand(pts, U.p, U.nx, V.p, Pu, pts[U.nx], Pv, 1, zs);
+    if (ok[1]) c[1] = make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs);
+    if (ok[2]) c[2] = make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs);
+    if (ok[3]) c[3] = make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs);
+    int sl[4];
+    ok[4] = U.cr < R.cntR[U.p];
+    ok[5] = U.cl < R.cntL[U.p];
+    ok[6] = V.cl < R.cntL[V.p];
+    ok[7] = V.cr < R.cntR[V.p];
+    if (ok[4]) c[4] = cand_of(R.ev_in, R.tau_in, sl[0] = R.entR[R.offR[U.p] + U.cr]);
+    if (ok[5]) c[5] = cand_of(R.ev_in, R.tau_in, sl[1] = R.entL[R.offL[U.p] + U.cl]);
+    if (ok[6]) c[6] = cand_of(R.ev_in, R.tau_in, sl[2] = R.entL[R.offL[V.p] + V.cl]);
+    if (ok[7]) c[7] = cand_of(R.ev_in, R.tau_in, sl[3] = R.entR[R.offR[V.p] + V.cr]);
+    int best = -1;
+    for (int l = 0; l < 8; ++l) {
+      if (!ok[l]) continue;
+      if (l < 4 && haveT && ev_cmp(pts, c[l], T, zs) <= 0) continue;
+      if (best < 0 || ev_cmp(pts, c[l], c[best], zs) < 0) best = l;
+    }
+    if (best < 0) break;
+    T = c[best];
+    haveT = true;
+    if (best >= 4) {  // a link change of an endpoint
+      Event E = R.ev_in[sl[best - 4]];
+      if (best == 4) { U.nx = right_after(E, U.p); ++U.cr; }
+      else if (best == 5) { U.pv = left_after(E, U.p); ++U.cl; }
+      else if (best == 6) { V.pv = left_after(E, V.p); ++V.cl; }
+      else { V.nx = right_after(E, V.p); ++V.cr; }
+      continue;
+    }
+    if (nb >= cap) {
+      atomicCAS(&h->err, 0, HULL_EINTERNAL);
+      break;
+    }
+    if (best == 0) { U.p = U.nx; Pu = pts[U.p]; lookup(R, U, true, T); }
+    else if (best == 1) { U.p = U.pv; Pu = pts[U.p]; lookup(R, U, true, T); }
+    else if (best == 2) { V.p = V.pv; Pv = pts[V.p]; lookup(R, V, true, T); }
+    else { V.p = V.nx; Pv = pts[V.p]; lookup(R, V, true, T); }
+    bout[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind};
+    btau[nb] = T.st;
+    buv[nb] = make_int2(U.p, V.p);
+    ++nb;
+  }
+  R.nB[s] = nb;
+  R.nx0[u0] = v0;
+  R.pv0[v0] = u0;
+}
+
+__global__ void __launch_bounds__(64) k_par_walk(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= P.merges) return;
+  int64_t width = int64_t(1) << P.k;
+  int64_t s = g * width, m = s + (width >> 1), e = std::min(s + width, P.n);
+  if (P.h->err) {
+    R.nB[s] = 0;
+    R.uv0[s] = make_int2(0, 0);
+    return;
+  }
+  walk_one(R, P.h, s, m, e);
+}
+
+// Survival of every child event, and the number of bridge events before it.
+__global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  const int k = P.k;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q <= 2 * P.n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    if (q == 2 * P.n || P.h->err) {
+      R.surv[q] = 0;
+      continue;
+    }
+    int64_t sb = in_block_start(q, k);
+    int64_t g = sb >> k;
+    if (g >= P.merges || q - 2 * sb >= R.len_in[sb]) {
+      R.surv[q] = 0;
+      continue;
+    }
+    int64_t s = g << k;
+    bool isL = sb == s;
+    Cand c = cand_of(R.ev_in, R.tau_in, q);
+    int nb = R.nB[s];
+    int j = count_before(R.pts, R.bev, R.btau, 2 * s, nb, c, R.zs);
+    int2 ref = j > 0 ? R.buv[2 * s + j - 1] : R.uv0[s];
+    R.surv[q] = isL ? (c.t.w < ref.x) : (c.t.w > ref.y);
+    R.jb[q] = j;
+  }
+}
+
+// Scatter: child survivors (indices [0, 2n)) and bridge events ([2n, 4n))
+// to their places in the merged movies.
+__global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  const bool err = P.h->err != 0;
+  const int k = P.k;
+  const int64_t n = P.n, width = int64_t(1) << k, half = width >> 1;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 4 * n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    if (t < 2 * n) {
+      int64_t q = t;
+      if (err || !R.surv[q]) continue;
+      int64_t sb = in_block_start(q, k);
+      int64_t s = (sb >> k) << k, m = s + half;
+      bool isL = sb == s;
+      Cand c = cand_of(R.ev_in, R.tau_in, q);
+      int64_t pos;
+      if (isL) {
+        int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, R.len_in[m], c, R.zs);
+        pos = (R.pre[q] - R.pre[2 * s]) + (R.pre[2 * m + idx] - R.pre[2 * m]) + R.jb[q];
+      } else {
+        int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, R.len_in[s], c, R.zs);
+        pos = (R.pre[2 * s + idx] - R.pre[2 * s]) + (R.pre[q] - R.pre[2 * m]) + R.jb[q];
+      }
+      if (pos >= 2 * (std::min(s + width, n) - s)) {
+        atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+        continue;
+      }
+      R.ev_out[2 * s + pos] = R.ev_in[q];
+      R.tau_out[2 * s + pos] = c.st;
+    } else {
+      int64_t q = t - 2 * n;
+      int64_t g = (q >> 1) >> k;
+      if (g >= P.merges) continue;
+      int64_t s = g << k, m = s + half, e = std::min(s + width, n);
+      int64_t j = q - 2 * s;
+      int nb = R.nB[s];
+      if (j == 0) {
+        // every merge writes its length, also after an error (then 0)
+        int cnt = err ? 0 : (R.pre[2 * e] - R.pre[2 * s]) + nb;
+        R.len_out[s] = cnt <= 2 * (e - s) ? cnt : 0;
+        if (cnt > 2 * (e - s)) atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+      }
+      if (err || j >= nb) continue;
+      Cand c = cand_of(R.bev, R.btau, q);
+      int iL = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, R.len_in[s], c, R.zs);
+      int iR = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, R.len_in[m], c, R.zs);
+      int64_t pos = j + (R.pre[2 * s + iL] - R.pre[2 * s]) + (R.pre[2 * m + iR] - R.pre[2 * m]);
+      if (pos >= 2 * (e - s)) {
+        atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+        continue;
+      }
+      R.ev_out[2 * s + pos] = R.bev[q];
+      R.tau_out[2 * s + pos] = c.st;
+    }
+  }
+}
+
+static unsigned blocks_for(int64_t work, int64_t cap = 8192) {
+  int64_t b = (work + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
+  const int64_t n = P.n;
+  dim3 runs(1, 2);
+  hipLaunchKernelGGL(k_par_zero, dim3(blocks_for(n), 2), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_par_count, dim3(blocks_for(2 * n), 2), dim3(256), 0, s, P);
+  for (int r = 0; r < 2; ++r) {
+    const ParRun& R = P.run[r];
+    if (!R.pts) continue;
+    int32_t rc = exclusive_scan_i32(R.cntR, R.offR, n, partials, s);
+    if (!rc) rc = exclusive_scan_i32(R.cntL, R.offL, n, partials, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_par_fill, dim3(blocks_for(2 * n), 2), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_par_sort, dim3(blocks_for(n), 2), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_par_walk, dim3((unsigned)((P.merges + 63) / 64), 2), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(k_par_classify, dim3(blocks_for(2 * n + 1), 2), dim3(256), 0, s, P);
+  for (int r = 0; r < 2; ++r) {
+    const ParRun& R = P.run[r];
+    if (!R.pts) continue;
+    int32_t rc = exclusive_scan_i32(R.surv, R.pre, 2 * n + 1, partials, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_par_scatter, dim3(blocks_for(4 * n), 2), dim3(256), 0, s, P);
+  HULL_LAUNCH_CHECK();
+  (void)runs;
+  return HULL_OK;
+}
+
+}  // namespace hull

@@ -260,7 +260,7 @@ Plan make_plan(int64_t n) {
   p.n = n;
   p.tiles = (nn + kTile - 1) / kTile;
   p.count_len = p.tiles * kBuckets;
-  p.partial_len = scan_partials_needed(p.count_len) + 1;
+  p.partial_len = std::max(scan_partials_needed(p.count_len), scan_partials_needed(2 * nn + 1)) + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -285,6 +285,22 @@ Plan make_plan(int64_t n) {
       p.tau[r][b] = take(2 * nn * sizeof(double));
       p.len[r][b] = take(nn * 4);
     }
+    p.cntR[r] = take(nn * 4);
+    p.cntL[r] = take(nn * 4);
+    p.offR[r] = take(nn * 4);
+    p.offL[r] = take(nn * 4);
+    p.curR[r] = take(nn * 4);
+    p.curL[r] = take(nn * 4);
+    p.entR[r] = take(4 * nn * 4);
+    p.entL[r] = take(4 * nn * 4);
+    p.bev[r] = take(2 * nn * sizeof(Event));
+    p.btau[r] = take(2 * nn * sizeof(double));
+    p.buv[r] = take(2 * nn * sizeof(int2));
+    p.nB[r] = take(nn * 4);
+    p.uv0[r] = take(nn * sizeof(int2));
+    p.surv[r] = take((2 * nn + 1) * 4);
+    p.jb[r] = take(2 * nn * 4);
+    p.pre[r] = take((2 * nn + 1) * 4);
   }
   p.total = off;
   return p;

@@ -40,6 +40,23 @@ def ws(H):
     return H.Workspace()
 
 
+# Merge strategies: every level lane-serial, every level parallel (bridge walk
+# and scatter), and the default split between them.  All must give the same
+# movies and faces.
+STRATEGIES = {"serial": "99", "parallel": "0", "default": ""}
+
+
+@pytest.fixture(params=sorted(STRATEGIES))
+def strategy(request):
+    old = os.environ.get("HULL_SERIAL_LEVELS")
+    os.environ["HULL_SERIAL_LEVELS"] = STRATEGIES[request.param]
+    yield request.param
+    if old is None:
+        os.environ.pop("HULL_SERIAL_LEVELS", None)
+    else:
+        os.environ["HULL_SERIAL_LEVELS"] = old
+
+
 def gpu_faces(H, ws, p, lower_only=False):
     import torch
     x = torch.from_numpy(np.ascontiguousarray(p, dtype=np.int32)).cuda()
@@ -101,23 +118,23 @@ def _cases(rng, count):
         yield t, p
 
 
-def test_degenerate_and_random_small(H, ws):
+def test_degenerate_and_random_small(H, ws, strategy):
     rng = np.random.default_rng(7)
     for t, p in _cases(rng, 270):
-        say("case", t, "n", len(p))
+        say("case", strategy, t, "n", len(p))
         assert same(gpu_faces(H, ws, p), oracle.hull(p)), t
 
 
 @pytest.mark.parametrize("n", [4, 5, 7, 31, 33, 100, 1000, 1025, 4097, 6000])
-def test_ragged_sizes(H, ws, n):
+def test_ragged_sizes(H, ws, n, strategy):
     rng = np.random.default_rng(n)
     p = workloads.cube(rng, n, 1 << 20) if n % 2 else workloads.lattice(rng, n, 40)
-    say("ragged n", n)
+    say("ragged n", n, strategy)
     assert same(gpu_faces(H, ws, p), oracle.hull(p))
     assert same(gpu_faces(H, ws, p, lower_only=True), oracle.hull(p, lower_only=True))
 
 
-def test_movies_every_level(H, ws):
+def test_movies_every_level(H, ws, strategy):
     import torch
     rng = np.random.default_rng(3)
     for t, n, kind in ((0, 300, "lattice"), (1, 777, "gauss"), (2, 1024, "sphere"), (3, 100, "flatx")):
@@ -134,7 +151,7 @@ def test_movies_every_level(H, ws):
         order = oracle.sort_order(p)
         for run in (0, 1):
             for level in range(1, oracle.levels_for(n) + 1):
-                say("movies", kind, "run", run, "level", level)
+                say("movies", strategy, kind, "run", run, "level", level)
                 ev, bl, gorder = H.movies(x, run, level, ws=ws)
                 assert (gorder == order).all()
                 want, wbl = oracle.level_movies(p, run, level)
@@ -147,12 +164,12 @@ def test_movies_every_level(H, ws):
                     pos += wbl[b]
 
 
-def test_range_error_reported_on_device(H, ws):
+def test_range_error_reported_on_device(H, ws, strategy):
     import torch
     p = workloads.cube(np.random.default_rng(1), 1000, 1 << 20)
     p[517, 1] = (1 << 29) + 1
     x = torch.from_numpy(p).cuda()
-    say("range error")
+    say("range error", strategy)
     faces, info = H.hull(x, ws=ws)
     st, F = (int(v) for v in info.cpu())
     assert st == H.HULL_ERANGE and F == 0
