@@ -35,6 +35,7 @@ struct Plan {
   size_t ev[2][2], tau[2][2], len[2][2];  // [run][buffer]
   // parallel merge strategy, per run
   size_t cntR[2], cntL[2], offR[2], offL[2], curR[2], curL[2], entR[2], entL[2];
+  size_t entRt[2], entLt[2], segS[2], segBase[2], segMerge[2], segCnt[2], segOff[2];
   size_t bev[2], btau[2], buv[2], nB[2], uv0[2], surv[2], jb[2], pre[2];
   size_t total;
   int64_t n, tiles, count_len, partial_len;

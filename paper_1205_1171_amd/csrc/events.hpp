@@ -101,8 +101,15 @@ struct ParRun {
   int* offL;
   int* curR;
   int* curL;
-  int* entR;  // event slots, grouped by point, time-sorted
-  int* entL;
+  Event* entR;    // link-change events grouped by point, time-sorted
+  double* entRt;  // their times
+  Event* entL;
+  double* entLt;
+  int* segS;      // per merge: # time segments of its bridge walk (merges + 1)
+  int* segBase;   // exclusive scan of segS
+  int* segMerge;  // per segment: its merge
+  int* segCnt;    // per segment: # bridge events
+  int* segOff;    // exclusive scan of segCnt
   Event* bev;  // bridge events of merge s at [2s, 2s + nB[s])
   double* btau;
   int2* buv;   // (u, v) after each bridge event
@@ -120,6 +127,8 @@ struct ParLevel {
   int64_t n;
   int k;           // level: input blocks of 2^(k-1) points, merged blocks of 2^k
   int64_t merges;  // merges per run (an unpaired trailing block is not one)
+  int seg_events;  // child events per walk segment
+  int64_t seg_cap; // bound on the number of segments of the level
 };
 
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s);

@@ -293,15 +293,21 @@ static unsigned grid_for(int64_t work, int64_t cap_blocks = 4096) {
   return (unsigned)b;
 }
 
-// Runs `levels` merge levels of the selected runs; returns the buffer index
-// holding the final movies.
 // Highest level merged by the lane-serial strategy; higher levels use the
 // parallel strategy.  Tunable through HULL_SERIAL_LEVELS (0 = parallel from
 // the first level, a large value = lane-serial throughout).
 static int serial_levels() {
   const char* e = getenv("HULL_SERIAL_LEVELS");
   if (e && *e) return atoi(e);
-  return 6;
+  return 12;
+}
+
+// Child events per time segment of a bridge walk (parallel strategy).
+// Tunable through HULL_WALK_SEGMENT.
+static int seg_events() {
+  const char* e = getenv("HULL_WALK_SEGMENT");
+  int v = (e && *e) ? atoi(e) : 2048;
+  return v < 8 ? 8 : v;
 }
 
 // Runs `levels` merge levels of the selected runs; returns the buffer index
@@ -336,8 +342,15 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     Q.offL = (int*)(ws + pl.offL[r]);
     Q.curR = (int*)(ws + pl.curR[r]);
     Q.curL = (int*)(ws + pl.curL[r]);
-    Q.entR = (int*)(ws + pl.entR[r]);
-    Q.entL = (int*)(ws + pl.entL[r]);
+    Q.entR = (Event*)(ws + pl.entR[r]);
+    Q.entL = (Event*)(ws + pl.entL[r]);
+    Q.entRt = (double*)(ws + pl.entRt[r]);
+    Q.entLt = (double*)(ws + pl.entLt[r]);
+    Q.segS = (int*)(ws + pl.segS[r]);
+    Q.segBase = (int*)(ws + pl.segBase[r]);
+    Q.segMerge = (int*)(ws + pl.segMerge[r]);
+    Q.segCnt = (int*)(ws + pl.segCnt[r]);
+    Q.segOff = (int*)(ws + pl.segOff[r]);
     Q.bev = (Event*)(ws + pl.bev[r]);
     Q.btau = (double*)(ws + pl.btau[r]);
     Q.buv = (int2*)(ws + pl.buv[r]);
@@ -387,6 +400,9 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
       } else {
         P.k = k;
         P.merges = A.merges;
+        P.seg_events = seg_events();
+        // sum over merges of 1 + (events)/G, events <= 2 * (points)
+        P.seg_cap = std::min<int64_t>(A.merges + (2 * n) / P.seg_events + 1, n);
         int32_t rc = parallel_level(P, partials, s);
         if (rc) return rc;
       }

@@ -75,6 +75,8 @@ __global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
   }
 }
 
+// Lists of link changes: every entry is the child event itself (its kind
+// field also carries its slot, kind | slot << 1, the sort key) and its time.
 __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts || P.h->err) return;
@@ -83,37 +85,41 @@ __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
     int64_t sb = in_block_start(q, P.k);
     if (q - 2 * sb >= R.len_in[sb]) continue;
     Event E = R.ev_in[q];
-    R.entR[R.offR[E.a] + atomicAdd(&R.curR[E.a], 1)] = (int)q;
-    R.entL[R.offL[E.b] + atomicAdd(&R.curL[E.b], 1)] = (int)q;
+    double t = R.tau_in[q];
+    Event X{E.a, E.w, E.b, (int)(q << 1) | E.kind};
+    int j = R.offR[E.a] + atomicAdd(&R.curR[E.a], 1);
+    R.entR[j] = X;
+    R.entRt[j] = t;
+    j = R.offL[E.b] + atomicAdd(&R.curL[E.b], 1);
+    R.entL[j] = X;
+    R.entLt[j] = t;
     if (E.kind) {
-      R.entR[R.offR[E.w] + atomicAdd(&R.curR[E.w], 1)] = (int)q;
-      R.entL[R.offL[E.w] + atomicAdd(&R.curL[E.w], 1)] = (int)q;
+      j = R.offR[E.w] + atomicAdd(&R.curR[E.w], 1);
+      R.entR[j] = X;
+      R.entRt[j] = t;
+      j = R.offL[E.w] + atomicAdd(&R.curL[E.w], 1);
+      R.entL[j] = X;
+      R.entLt[j] = t;
     }
   }
 }
 
-__device__ void sort_slots(int* a, int k) {
-  if (k <= 24) {
-    for (int i = 1; i < k; ++i) {
-      int x = a[i], j = i - 1;
-      while (j >= 0 && a[j] > x) {
-        a[j + 1] = a[j];
-        --j;
-      }
-      a[j + 1] = x;
-    }
-    return;
-  }
+// Sort one point's entries by slot (= time order within the child movie).
+__device__ void sort_entries(Event* a, double* t, int k) {
   int gap = 1;
   while (gap < k / 3) gap = 3 * gap + 1;
   for (; gap > 0; gap /= 3)
     for (int i = gap; i < k; ++i) {
-      int x = a[i], j = i;
-      while (j >= gap && a[j - gap] > x) {
+      Event x = a[i];
+      double y = t[i];
+      int j = i;
+      while (j >= gap && a[j - gap].kind > x.kind) {
         a[j] = a[j - gap];
+        t[j] = t[j - gap];
         j -= gap;
       }
       a[j] = x;
+      t[j] = y;
     }
 }
 
@@ -122,27 +128,36 @@ __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
   if (!R.pts || P.h->err) return;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
        p += (int64_t)gridDim.x * blockDim.x) {
-    sort_slots(R.entR + R.offR[p], R.cntR[p]);
-    sort_slots(R.entL + R.offL[p], R.cntL[p]);
+    sort_entries(R.entR + R.offR[p], R.entRt + R.offR[p], R.cntR[p]);
+    sort_entries(R.entL + R.offL[p], R.entLt + R.offL[p], R.cntL[p]);
   }
 }
 
 // Link of p after an event that changes it.
 __device__ __forceinline__ int right_after(const Event& E, int p) {
-  return p == E.a ? (E.kind ? E.w : E.b) : E.b;
+  return p == E.a ? ((E.kind & 1) ? E.w : E.b) : E.b;
 }
 __device__ __forceinline__ int left_after(const Event& E, int p) {
-  return p == E.b ? (E.kind ? E.w : E.a) : E.a;
+  return p == E.b ? ((E.kind & 1) ? E.w : E.a) : E.a;
+}
+
+__device__ __forceinline__ Cand cand_entry(const Event* e, const double* t, int j) {
+  Event E = e[j];
+  Cand c;
+  c.t = Tri{E.a, E.w, E.b};
+  c.kind = E.kind & 1;
+  c.st = t[j];
+  return c;
 }
 
 // Position in a point's list of its first change strictly after T.
-__device__ int first_after(const ParRun& R, const int* ent, int off, int cnt, bool haveT,
-                           const Cand& T) {
+__device__ int first_after(const ParRun& R, const Event* e, const double* t, int off, int cnt,
+                           bool haveT, const Cand& T) {
   if (!haveT) return 0;
   int lo = 0, hi = cnt;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    Cand c = cand_of(R.ev_in, R.tau_in, ent[off + mid]);
+    Cand c = cand_entry(e, t, off + mid);
     if (ev_cmp(R.pts, c, T, R.zs) > 0) hi = mid;
     else lo = mid + 1;
   }
@@ -150,69 +165,107 @@ __device__ int first_after(const ParRun& R, const int* ent, int off, int cnt, bo
 }
 
 struct Endpoint {
-  int p;      // the point
-  int nx, pv; // its links at the current time
-  int cr, cl; // next unprocessed change in its right / left list
+  int p;       // the point
+  int nx, pv;  // its links at the current time
+  int cr, cl;  // next unprocessed change in its right / left list
+  int oR, nR, oL, nL;
 };
 
 __device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) {
   int p = X.p;
-  int oR = R.offR[p], nR = R.cntR[p], oL = R.offL[p], nL = R.cntL[p];
-  X.cr = first_after(R, R.entR, oR, nR, haveT, T);
-  X.cl = first_after(R, R.entL, oL, nL, haveT, T);
-  X.nx = X.cr > 0 ? right_after(R.ev_in[R.entR[oR + X.cr - 1]], p) : R.nx0[p];
-  X.pv = X.cl > 0 ? left_after(R.ev_in[R.entL[oL + X.cl - 1]], p) : R.pv0[p];
+  X.oR = R.offR[p];
+  X.nR = R.cntR[p];
+  X.oL = R.offL[p];
+  X.nL = R.cntL[p];
+  X.cr = first_after(R, R.entR, R.entRt, X.oR, X.nR, haveT, T);
+  X.cl = first_after(R, R.entL, R.entLt, X.oL, X.nL, haveT, T);
+  X.nx = X.cr > 0 ? right_after(R.entR[X.oR + X.cr - 1], p) : R.nx0[p];
+  X.pv = X.cl > 0 ? left_after(R.entL[X.oL + X.cl - 1], p) : R.pv0[p];
 }
 
-__device__ void walk_one(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e) {
+// Orientation of the rank-ordered triple (a, b, c) just after event T: its
+// sign at t = -inf is sign(D), and it flips once, at its own event.
+__device__ int orient_after(const int4* pts, int a, int b, int c, const Cand& T, int zs) {
+  int4 A = pts[a], B = pts[b], C = pts[c];
+  int ds = d_sign(A, B, C);
+  Cand x = make_cand(pts, a, b, c, A, B, C, 0, zs);
+  return ev_cmp(pts, x, T, zs) > 0 ? ds : -ds;
+}
+
+// Segment i of S of a merge covers the events after boundary b_i up to and
+// including b_(i+1), b_0 = -inf, b_S = +inf; b_i (0 < i < S) is the event at
+// index floor(i * n / S) of the longer child movie.
+__device__ __forceinline__ int64_t boundary_slot(const ParRun& R, int64_t s, int64_t m, int i,
+                                                 int S) {
+  int nL = R.len_in[s], nR = R.len_in[m];
+  int64_t base = nL >= nR ? 2 * s : 2 * m;
+  int64_t nn = nL >= nR ? nL : nR;
+  return base + (int64_t)i * nn / S;
+}
+
+__device__ __forceinline__ int segments_for(int nL, int nR, int G) {
+  int nn = nL > nR ? nL : nR;
+  int S = 1 + (nL + nR) / G;
+  return S > nn + 1 ? nn + 1 : S;
+}
+
+// The bridge walk over one time segment.  Returns the number of bridge
+// events in the segment; with `out` set, writes them there (and their
+// bridges after each move to `out_uv`).  Segment 0 also reports the -inf
+// bridge in `uv0`.
+__device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e, int seg,
+                            int S, Event* out, double* out_tau, int2* out_uv, int cap,
+                            int2* uv0) {
   const int4* pts = R.pts;
   const int zs = R.zs;
-  // bridge at t = -inf
-  int u = (int)m - 1, v = (int)m;
-  int4 Pu = pts[u], Pv = pts[v];
+  bool haveT = false, haveEnd = false;
+  Cand T, Tend;
+  T.t = Tri{-1, -1, -1};
+  T.st = 0.0;
+  T.kind = 0;
+  Tend = T;
+  if (seg > 0) {
+    T = cand_of(R.ev_in, R.tau_in, boundary_slot(R, s, m, seg, S));
+    haveT = true;
+  }
+  if (seg + 1 < S) {
+    Tend = cand_of(R.ev_in, R.tau_in, boundary_slot(R, s, m, seg + 1, S));
+    haveEnd = true;
+  }
+  // the bridge at the start of the segment: walk to the lower common tangent
+  // of the two chains, from the inner ends of the blocks
+  Endpoint U{(int)m - 1, 0, 0, 0, 0, 0, 0, 0, 0}, V{(int)m, 0, 0, 0, 0, 0, 0, 0, 0};
+  lookup(R, U, haveT, T);
+  lookup(R, V, haveT, T);
   for (int guard = 0;; ++guard) {
     if (guard > 2 * (e - s) + 4) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
-      R.nB[s] = 0;
-      return;
+      return 0;
     }
-    int w = R.nx0[v];
-    if (w != kNil) {
-      int4 Pw = pts[w];
-      if (d_sign(Pu, Pv, Pw) < 0) {
-        v = w;
-        Pv = Pw;
+    if (V.nx != kNil) {
+      int o = haveT ? orient_after(pts, U.p, V.p, V.nx, T, zs)
+                    : d_sign(pts[U.p], pts[V.p], pts[V.nx]);
+      if (o < 0) {
+        V.p = V.nx;
+        lookup(R, V, haveT, T);
         continue;
       }
     }
-    w = R.pv0[u];
-    if (w != kNil) {
-      int4 Pw = pts[w];
-      if (d_sign(Pw, Pu, Pv) < 0) {
-        u = w;
-        Pu = Pw;
+    if (U.pv != kNil) {
+      int o = haveT ? orient_after(pts, U.pv, U.p, V.p, T, zs)
+                    : d_sign(pts[U.pv], pts[U.p], pts[V.p]);
+      if (o < 0) {
+        U.p = U.pv;
+        lookup(R, U, haveT, T);
         continue;
       }
     }
     break;
   }
-  const int u0 = u, v0 = v;
-  R.uv0[s] = make_int2(u0, v0);
-
-  bool haveT = false;
-  Cand T;
-  T.t = Tri{-1, -1, -1};
-  T.st = 0.0;
-  T.kind = 0;
-  Endpoint U{u, 0, 0, 0, 0}, V{v, 0, 0, 0, 0};
-  lookup(R, U, haveT, T);
-  lookup(R, V, haveT, T);
+  if (uv0) *uv0 = make_int2(U.p, V.p);
+  int4 Pu = pts[U.p], Pv = pts[V.p];
   int nb = 0;
-  const int64_t cap = 2 * (e - s);
   const int64_t iter_cap = (int64_t)R.len_in[s] + R.len_in[m] + 4 * (e - s) + 16;
-  Event* bout = R.bev + 2 * s;
-  double* btau = R.btau + 2 * s;
-  int2* buv = R.buv + 2 * s;
   for (int64_t it = 0;; ++it) {
     if (it > iter_cap) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
@@ -225,19 +278,18 @@ __device__ void walk_one(const ParRun& R, Header* h, int64_t s, int64_t m, int64
     ok[1] = U.pv != kNil;
     ok[2] = V.pv != kNil;
     ok[3] = V.nx != kNil;
+    ok[4] = U.cr < U.nR;
+    ok[5] = U.cl < U.nL;
+    ok[6] = V.cl < V.nL;
+    ok[7] = V.cr < V.nR;
+    if (ok[4]) c[4] = cand_entry(R.entR, R.entRt, U.oR + U.cr);
+    if (ok[5]) c[5] = cand_entry(R.entL, R.entLt, U.oL + U.cl);
+    if (ok[6]) c[6] = cand_entry(R.entL, R.entLt, V.oL + V.cl);
+    if (ok[7]) c[7] = cand_entry(R.entR, R.entRt, V.oR + V.cr);
     if (ok[0]) c[0] = make_cand(pts, U.p, U.nx, V.p, Pu, pts[U.nx], Pv, 1, zs);
     if (ok[1]) c[1] = make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs);
     if (ok[2]) c[2] = make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs);
     if (ok[3]) c[3] = make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs);
-    int sl[4];
-    ok[4] = U.cr < R.cntR[U.p];
-    ok[5] = U.cl < R.cntL[U.p];
-    ok[6] = V.cl < R.cntL[V.p];
-    ok[7] = V.cr < R.cntR[V.p];
-    if (ok[4]) c[4] = cand_of(R.ev_in, R.tau_in, sl[0] = R.entR[R.offR[U.p] + U.cr]);
-    if (ok[5]) c[5] = cand_of(R.ev_in, R.tau_in, sl[1] = R.entL[R.offL[U.p] + U.cl]);
-    if (ok[6]) c[6] = cand_of(R.ev_in, R.tau_in, sl[2] = R.entL[R.offL[V.p] + V.cl]);
-    if (ok[7]) c[7] = cand_of(R.ev_in, R.tau_in, sl[3] = R.entR[R.offR[V.p] + V.cr]);
     int best = -1;
     for (int l = 0; l < 8; ++l) {
       if (!ok[l]) continue;
@@ -245,47 +297,100 @@ __device__ void walk_one(const ParRun& R, Header* h, int64_t s, int64_t m, int64
       if (best < 0 || ev_cmp(pts, c[l], c[best], zs) < 0) best = l;
     }
     if (best < 0) break;
+    if (haveEnd && ev_cmp(pts, c[best], Tend, zs) > 0) break;
     T = c[best];
     haveT = true;
     if (best >= 4) {  // a link change of an endpoint
-      Event E = R.ev_in[sl[best - 4]];
-      if (best == 4) { U.nx = right_after(E, U.p); ++U.cr; }
-      else if (best == 5) { U.pv = left_after(E, U.p); ++U.cl; }
-      else if (best == 6) { V.pv = left_after(E, V.p); ++V.cl; }
-      else { V.nx = right_after(E, V.p); ++V.cr; }
+      if (best == 4) { U.nx = right_after(R.entR[U.oR + U.cr], U.p); ++U.cr; }
+      else if (best == 5) { U.pv = left_after(R.entL[U.oL + U.cl], U.p); ++U.cl; }
+      else if (best == 6) { V.pv = left_after(R.entL[V.oL + V.cl], V.p); ++V.cl; }
+      else { V.nx = right_after(R.entR[V.oR + V.cr], V.p); ++V.cr; }
       continue;
     }
-    if (nb >= cap) {
-      atomicCAS(&h->err, 0, HULL_EINTERNAL);
-      break;
+    if (best == 0) U.p = U.nx;
+    else if (best == 1) U.p = U.pv;
+    else if (best == 2) V.p = V.pv;
+    else V.p = V.nx;
+    if (best <= 1) {
+      Pu = pts[U.p];
+      lookup(R, U, true, T);
+    } else {
+      Pv = pts[V.p];
+      lookup(R, V, true, T);
     }
-    if (best == 0) { U.p = U.nx; Pu = pts[U.p]; lookup(R, U, true, T); }
-    else if (best == 1) { U.p = U.pv; Pu = pts[U.p]; lookup(R, U, true, T); }
-    else if (best == 2) { V.p = V.pv; Pv = pts[V.p]; lookup(R, V, true, T); }
-    else { V.p = V.nx; Pv = pts[V.p]; lookup(R, V, true, T); }
-    bout[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind};
-    btau[nb] = T.st;
-    buv[nb] = make_int2(U.p, V.p);
+    if (out) {
+      if (nb >= cap) {
+        atomicCAS(&h->err, 0, HULL_EINTERNAL);
+        break;
+      }
+      out[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind};
+      out_tau[nb] = T.st;
+      out_uv[nb] = make_int2(U.p, V.p);
+    }
     ++nb;
   }
-  R.nB[s] = nb;
-  R.nx0[u0] = v0;
-  R.pv0[v0] = u0;
+  return nb;
 }
 
-__global__ void __launch_bounds__(64) k_par_walk(ParLevel P) {
+// Segments per merge, from the child movie lengths.
+__global__ void __launch_bounds__(256) k_par_segcount(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= P.merges) return;
-  int64_t width = int64_t(1) << P.k;
-  int64_t s = g * width, m = s + (width >> 1), e = std::min(s + width, P.n);
-  if (P.h->err) {
-    R.nB[s] = 0;
-    R.uv0[s] = make_int2(0, 0);
+  const int64_t width = int64_t(1) << P.k;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g <= P.merges;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    if (g == P.merges || P.h->err) {
+      R.segS[g] = g == P.merges ? 0 : 1;
+      continue;
+    }
+    int64_t s = g * width, m = s + (width >> 1);
+    R.segS[g] = segments_for(R.len_in[s], R.len_in[m], P.seg_events);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.merges;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int b = R.segBase[g], S = R.segS[g];
+    for (int i = 0; i < S; ++i) R.segMerge[b + i] = (int)g;
+  }
+}
+
+// Pass 1 counts each segment's bridge events; pass 2 writes them at their
+// place in the merge's bridge list.
+__global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t > P.seg_cap) return;
+  const int total = R.segBase[P.merges];
+  if (t >= total) {
+    if (!write) R.segCnt[t] = 0;
     return;
   }
-  walk_one(R, P.h, s, m, e);
+  const int g = R.segMerge[t];
+  const int first = R.segBase[g], S = R.segS[g], i = (int)(t - first);
+  const int64_t width = int64_t(1) << P.k;
+  const int64_t s = g * width, m = s + (width >> 1), e = std::min(s + width, P.n);
+  if (P.h->err) {
+    if (!write) R.segCnt[t] = 0;
+    else if (i == 0) {
+      R.nB[s] = 0;
+      R.uv0[s] = make_int2(0, 0);
+    }
+    return;
+  }
+  if (!write) {
+    R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, nullptr, 0, nullptr);
+    return;
+  }
+  int64_t off = R.segOff[t] - R.segOff[first];
+  int cap = (int)(2 * (e - s) - off);
+  walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.btau + 2 * s + off,
+               R.buv + 2 * s + off, cap, i == 0 ? &R.uv0[s] : nullptr);
+  if (i == 0) R.nB[s] = R.segOff[first + S] - R.segOff[first];
 }
 
 // Survival of every child event, and the number of bridge events before it.
@@ -359,6 +464,13 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
         int cnt = err ? 0 : (R.pre[2 * e] - R.pre[2 * s]) + nb;
         R.len_out[s] = cnt <= 2 * (e - s) ? cnt : 0;
         if (cnt > 2 * (e - s)) atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+        // splice the -inf chains at the -inf bridge (no kernel of this level
+        // reads the -inf links after the walk)
+        if (!err) {
+          int2 b0 = R.uv0[s];
+          R.nx0[b0.x] = b0.y;
+          R.pv0[b0.y] = b0.x;
+        }
       }
       if (err || j >= nb) continue;
       Cand c = cand_of(R.bev, R.btau, q);
@@ -384,19 +496,29 @@ static unsigned blocks_for(int64_t work, int64_t cap = 8192) {
 
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   const int64_t n = P.n;
-  dim3 runs(1, 2);
   hipLaunchKernelGGL(k_par_zero, dim3(blocks_for(n), 2), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_par_count, dim3(blocks_for(2 * n), 2), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_par_segcount, dim3(blocks_for(P.merges + 1), 2), dim3(256), 0, s, P);
   for (int r = 0; r < 2; ++r) {
     const ParRun& R = P.run[r];
     if (!R.pts) continue;
     int32_t rc = exclusive_scan_i32(R.cntR, R.offR, n, partials, s);
     if (!rc) rc = exclusive_scan_i32(R.cntL, R.offL, n, partials, s);
+    if (!rc) rc = exclusive_scan_i32(R.segS, R.segBase, P.merges + 1, partials, s);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_par_fill, dim3(blocks_for(2 * n), 2), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_par_sort, dim3(blocks_for(n), 2), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_par_walk, dim3((unsigned)((P.merges + 63) / 64), 2), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(k_par_segtable, dim3(blocks_for(P.merges), 2), dim3(256), 0, s, P);
+  const unsigned wg = (unsigned)((P.seg_cap + 1 + 63) / 64);
+  hipLaunchKernelGGL(k_par_walk, dim3(wg, 2), dim3(64), 0, s, P, 0);
+  for (int r = 0; r < 2; ++r) {
+    const ParRun& R = P.run[r];
+    if (!R.pts) continue;
+    int32_t rc = exclusive_scan_i32(R.segCnt, R.segOff, P.seg_cap + 1, partials, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_par_walk, dim3(wg, 2), dim3(64), 0, s, P, 1);
   hipLaunchKernelGGL(k_par_classify, dim3(blocks_for(2 * n + 1), 2), dim3(256), 0, s, P);
   for (int r = 0; r < 2; ++r) {
     const ParRun& R = P.run[r];
@@ -406,7 +528,6 @@ int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_par_scatter, dim3(blocks_for(4 * n), 2), dim3(256), 0, s, P);
   HULL_LAUNCH_CHECK();
-  (void)runs;
   return HULL_OK;
 }
 

@@ -291,8 +291,15 @@ Plan make_plan(int64_t n) {
     p.offL[r] = take(nn * 4);
     p.curR[r] = take(nn * 4);
     p.curL[r] = take(nn * 4);
-    p.entR[r] = take(4 * nn * 4);
-    p.entL[r] = take(4 * nn * 4);
+    p.entR[r] = take(4 * nn * sizeof(Event));
+    p.entL[r] = take(4 * nn * sizeof(Event));
+    p.entRt[r] = take(4 * nn * sizeof(double));
+    p.entLt[r] = take(4 * nn * sizeof(double));
+    p.segS[r] = take((nn + 2) * 4);
+    p.segBase[r] = take((nn + 2) * 4);
+    p.segMerge[r] = take((nn + 2) * 4);
+    p.segCnt[r] = take((nn + 2) * 4);
+    p.segOff[r] = take((nn + 2) * 4);
     p.bev[r] = take(2 * nn * sizeof(Event));
     p.btau[r] = take(2 * nn * sizeof(double));
     p.buv[r] = take(2 * nn * sizeof(int2));

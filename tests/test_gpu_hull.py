@@ -43,18 +43,26 @@ def ws(H):
 # Merge strategies: every level lane-serial, every level parallel (bridge walk
 # and scatter), and the default split between them.  All must give the same
 # movies and faces.
-STRATEGIES = {"serial": "99", "parallel": "0", "default": ""}
+# The parallel strategy is also run with walk segments of 8 child events, so
+# that most walks start from a tangent found at a segment boundary.
+STRATEGIES = {
+    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": ""},
+    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": ""},
+    "parallel_seg8": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "8"},
+    "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": ""},
+}
 
 
 @pytest.fixture(params=sorted(STRATEGIES))
 def strategy(request):
-    old = os.environ.get("HULL_SERIAL_LEVELS")
-    os.environ["HULL_SERIAL_LEVELS"] = STRATEGIES[request.param]
+    saved = {k: os.environ.get(k) for k in STRATEGIES[request.param]}
+    os.environ.update(STRATEGIES[request.param])
     yield request.param
-    if old is None:
-        os.environ.pop("HULL_SERIAL_LEVELS", None)
-    else:
-        os.environ["HULL_SERIAL_LEVELS"] = old
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
 
 
 def gpu_faces(H, ws, p, lower_only=False):
@@ -187,6 +195,8 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
+        os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
     assert len(p) == rec["n"]
