@@ -36,16 +36,17 @@ struct LevelArgs {
   int64_t merges; // merges per run
 };
 
-// Exact (time, rank triple) order of two distinct-or-equal events.
-__device__ __noinline__ int ev_cmp_exact(const int4* pts, const Cand& A, const Cand& B, int zs) {
+// Exact (time, rank triple) order of two events (cold path).  Arguments
+// go by value so that callers keep their candidates in registers.
+__device__ __noinline__ int tri_cmp_exact(const int4* pts, Tri A, Tri B, int zs) {
   Coef ca, cb;
-  coef_of(pts[A.t.a], pts[A.t.w], pts[A.t.b], zs, ca);
-  coef_of(pts[B.t.a], pts[B.t.w], pts[B.t.b], zs, cb);
+  coef_of(pts[A.a], pts[A.w], pts[A.b], zs, ca);
+  coef_of(pts[B.a], pts[B.w], pts[B.b], zs, cb);
   int s = tau_cmp_exact(ca, cb);
   if (s) return s;
-  if (A.t.a != B.t.a) return A.t.a < B.t.a ? -1 : 1;
-  if (A.t.w != B.t.w) return A.t.w < B.t.w ? -1 : 1;
-  if (A.t.b != B.t.b) return A.t.b < B.t.b ? -1 : 1;
+  if (A.a != B.a) return A.a < B.a ? -1 : 1;
+  if (A.w != B.w) return A.w < B.w ? -1 : 1;
+  if (A.b != B.b) return A.b < B.b ? -1 : 1;
   return 0;
 }
 
@@ -53,17 +54,24 @@ __device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand
   if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
   int s = std_cmp(A.st, B.st);
   if (s) return s;
-  return ev_cmp_exact(pts, A, B, zs);
+  return tri_cmp_exact(pts, A.t, B.t, zs);
+}
+
+// Perturbed sign of D when D0 = D1 = 0 (cold path).
+__device__ __noinline__ int d_sign_slow(int4 P, int4 Q, int4 R) {
+  Coef c;
+  coef_of(P, Q, R, 1, c);
+  return c.dsign;
 }
 
 // Perturbed sign of D(a, b, c) (xy orientation).
 __device__ __forceinline__ int d_sign(int4 P, int4 Q, int4 R) {
-  int64_t D0 = ((int64_t)Q.x - P.x) * ((int64_t)R.y - P.y) -
-               ((int64_t)R.x - P.x) * ((int64_t)Q.y - P.y);
+  int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
+  int64_t D0 = ((int64_t)Q.x - P.x) * dy2 - ((int64_t)R.x - P.x) * dy1;
   if (D0) return D0 > 0 ? 1 : -1;
-  Coef c;
-  coef_of(P, Q, R, 1, c);
-  return c.dsign;
+  int64_t D1 = ((int64_t)Q.w - P.w) * dy2 - ((int64_t)R.w - P.w) * dy1;
+  if (D1) return D1 > 0 ? 1 : -1;
+  return d_sign_slow(P, Q, R);
 }
 
 __device__ __forceinline__ Cand make_cand(const int4* pts, int a, int w, int b, int4 A, int4 W,

@@ -94,48 +94,46 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
       break;
     }
-    Cand c[6];
-    bool ok[6];
+    // candidates: 0 next L event, 1 next R event, 2..5 bridge moves; the
+    // indices are compile-time constants so that the candidates stay in
+    // registers
+    Cand best;
+    int bi = -1;
+    auto consider = [&](int idx, const Cand& c) {
+      if (haveT && ev_cmp(pts, c, T, zs) <= 0) return;
+      if (bi < 0 || ev_cmp(pts, c, best, zs) < 0) {
+        best = c;
+        bi = idx;
+      }
+    };
     if (i < nL) {
       Event E = Lev[i];
-      c[0].t = Tri{E.a, E.w, E.b};
-      c[0].kind = E.kind;
-      c[0].st = Ltau[i];
-      ok[0] = true;
-    } else {
-      ok[0] = false;
+      Cand c;
+      c.t = Tri{E.a, E.w, E.b};
+      c.kind = E.kind;
+      c.st = Ltau[i];
+      consider(0, c);
     }
     if (j < nR) {
       Event E = Rev[j];
-      c[1].t = Tri{E.a, E.w, E.b};
-      c[1].kind = E.kind;
-      c[1].st = Rtau[j];
-      ok[1] = true;
-    } else {
-      ok[1] = false;
+      Cand c;
+      c.t = Tri{E.a, E.w, E.b};
+      c.kind = E.kind;
+      c.st = Rtau[j];
+      consider(1, c);
     }
-    int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
-    ok[2] = nu != kNil;
-    ok[3] = pu != kNil;
-    ok[4] = pvv != kNil;
-    ok[5] = nv != kNil;
-    if (ok[2]) c[2] = make_cand(pts, u, nu, v, Pu, pts[nu], Pv, 1, zs);
-    if (ok[3]) c[3] = make_cand(pts, pu, u, v, pts[pu], Pu, Pv, 0, zs);
-    if (ok[4]) c[4] = make_cand(pts, u, pvv, v, Pu, pts[pvv], Pv, 1, zs);
-    if (ok[5]) c[5] = make_cand(pts, u, v, nv, Pu, Pv, pts[nv], 0, zs);
-    int best = -1;
-    for (int l = 0; l < 6; ++l) {
-      if (!ok[l]) continue;
-      if (haveT && ev_cmp(pts, c[l], T, zs) <= 0) continue;
-      if (best < 0 || ev_cmp(pts, c[l], c[best], zs) < 0) best = l;
-    }
-    if (best < 0) break;
-    T = c[best];
+    const int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
+    if (nu != kNil) consider(2, make_cand(pts, u, nu, v, Pu, pts[nu], Pv, 1, zs));
+    if (pu != kNil) consider(3, make_cand(pts, pu, u, v, pts[pu], Pu, Pv, 0, zs));
+    if (pvv != kNil) consider(4, make_cand(pts, u, pvv, v, Pu, pts[pvv], Pv, 1, zs));
+    if (nv != kNil) consider(5, make_cand(pts, u, v, nv, Pu, Pv, pts[nv], 0, zs));
+    if (bi < 0) break;
+    T = best;
     haveT = true;
     bool emit = false;
-    if (best <= 1) {
+    if (bi <= 1) {
       const Tri& t = T.t;
-      emit = best == 0 ? (t.w < u) : (t.w > v);
+      emit = bi == 0 ? (t.w < u) : (t.w > v);
       if (T.kind) {  // insertion into the child's chain
         nx[t.a] = t.w;
         pv[t.b] = t.w;
@@ -145,12 +143,12 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
         nx[t.a] = t.b;
         pv[t.b] = t.a;
       }
-      if (best == 0) ++i; else ++j;
+      if (bi == 0) ++i; else ++j;
     } else {
       emit = true;
-      if (best == 2) { u = nu; Pu = pts[u]; }
-      else if (best == 3) { u = pu; Pu = pts[u]; }
-      else if (best == 4) { v = pvv; Pv = pts[v]; }
+      if (bi == 2) { u = nu; Pu = pts[u]; }
+      else if (bi == 3) { u = pu; Pu = pts[u]; }
+      else if (bi == 4) { v = pvv; Pv = pts[v]; }
       else { v = nv; Pv = pts[v]; }
     }
     if (emit) {

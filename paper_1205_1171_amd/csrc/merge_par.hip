@@ -271,47 +271,42 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
       break;
     }
-    // candidates: 0..3 bridge moves, 4..7 next link changes of u and v
-    Cand c[8];
-    bool ok[8];
-    ok[0] = U.nx != kNil;
-    ok[1] = U.pv != kNil;
-    ok[2] = V.pv != kNil;
-    ok[3] = V.nx != kNil;
-    ok[4] = U.cr < U.nR;
-    ok[5] = U.cl < U.nL;
-    ok[6] = V.cl < V.nL;
-    ok[7] = V.cr < V.nR;
-    if (ok[4]) c[4] = cand_entry(R.entR, R.entRt, U.oR + U.cr);
-    if (ok[5]) c[5] = cand_entry(R.entL, R.entLt, U.oL + U.cl);
-    if (ok[6]) c[6] = cand_entry(R.entL, R.entLt, V.oL + V.cl);
-    if (ok[7]) c[7] = cand_entry(R.entR, R.entRt, V.oR + V.cr);
-    if (ok[0]) c[0] = make_cand(pts, U.p, U.nx, V.p, Pu, pts[U.nx], Pv, 1, zs);
-    if (ok[1]) c[1] = make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs);
-    if (ok[2]) c[2] = make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs);
-    if (ok[3]) c[3] = make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs);
-    int best = -1;
-    for (int l = 0; l < 8; ++l) {
-      if (!ok[l]) continue;
-      if (l < 4 && haveT && ev_cmp(pts, c[l], T, zs) <= 0) continue;
-      if (best < 0 || ev_cmp(pts, c[l], c[best], zs) < 0) best = l;
-    }
-    if (best < 0) break;
-    if (haveEnd && ev_cmp(pts, c[best], Tend, zs) > 0) break;
-    T = c[best];
+    // candidates: 0..3 bridge moves (checked against T), 4..7 the next link
+    // changes of u and v (after T by construction); all indices below are
+    // compile-time constants so that the candidates stay in registers
+    Cand best;
+    int bi = -1;
+    auto consider = [&](int idx, const Cand& c) {
+      if (idx < 4 && haveT && ev_cmp(pts, c, T, zs) <= 0) return;
+      if (bi < 0 || ev_cmp(pts, c, best, zs) < 0) {
+        best = c;
+        bi = idx;
+      }
+    };
+    if (U.nx != kNil) consider(0, make_cand(pts, U.p, U.nx, V.p, Pu, pts[U.nx], Pv, 1, zs));
+    if (U.pv != kNil) consider(1, make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs));
+    if (V.pv != kNil) consider(2, make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs));
+    if (V.nx != kNil) consider(3, make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs));
+    if (U.cr < U.nR) consider(4, cand_entry(R.entR, R.entRt, U.oR + U.cr));
+    if (U.cl < U.nL) consider(5, cand_entry(R.entL, R.entLt, U.oL + U.cl));
+    if (V.cl < V.nL) consider(6, cand_entry(R.entL, R.entLt, V.oL + V.cl));
+    if (V.cr < V.nR) consider(7, cand_entry(R.entR, R.entRt, V.oR + V.cr));
+    if (bi < 0) break;
+    if (haveEnd && ev_cmp(pts, best, Tend, zs) > 0) break;
+    T = best;
     haveT = true;
-    if (best >= 4) {  // a link change of an endpoint
-      if (best == 4) { U.nx = right_after(R.entR[U.oR + U.cr], U.p); ++U.cr; }
-      else if (best == 5) { U.pv = left_after(R.entL[U.oL + U.cl], U.p); ++U.cl; }
-      else if (best == 6) { V.pv = left_after(R.entL[V.oL + V.cl], V.p); ++V.cl; }
+    if (bi >= 4) {  // a link change of an endpoint
+      if (bi == 4) { U.nx = right_after(R.entR[U.oR + U.cr], U.p); ++U.cr; }
+      else if (bi == 5) { U.pv = left_after(R.entL[U.oL + U.cl], U.p); ++U.cl; }
+      else if (bi == 6) { V.pv = left_after(R.entL[V.oL + V.cl], V.p); ++V.cl; }
       else { V.nx = right_after(R.entR[V.oR + V.cr], V.p); ++V.cr; }
       continue;
     }
-    if (best == 0) U.p = U.nx;
-    else if (best == 1) U.p = U.pv;
-    else if (best == 2) V.p = V.pv;
+    if (bi == 0) U.p = U.nx;
+    else if (bi == 1) U.p = U.pv;
+    else if (bi == 2) V.p = V.pv;
     else V.p = V.nx;
-    if (best <= 1) {
+    if (bi <= 1) {
       Pu = pts[U.p];
       lookup(R, U, true, T);
     } else {
