@@ -11,6 +11,13 @@ namespace hull {
 constexpr int kNil = -1;
 constexpr int64_t kMaxN = int64_t(1) << 26;
 constexpr int32_t kMaxCoord = 1 << 29;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kTile = kSortThreads * kSortItems;  // keys per radix tile
+constexpr int kRadixBits = 8;
+constexpr int kBuckets = 1 << kRadixBits;
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = kSortThreads * kScanItems;
 
 // Device-side status words at the head of every workspace.
 struct Header {

@@ -97,7 +97,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     // candidates: 0 next L event, 1 next R event, 2..5 bridge moves; the
     // indices are compile-time constants so that the candidates stay in
     // registers
-    Cand best;
+    Cand best = T;  // defined value: only read once bi >= 0
     int bi = -1;
     auto consider = [&](int idx, const Cand& c) {
       if (haveT && ev_cmp(pts, c, T, zs) <= 0) return;

@@ -274,7 +274,7 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
     // candidates: 0..3 bridge moves (checked against T), 4..7 the next link
     // changes of u and v (after T by construction); all indices below are
     // compile-time constants so that the candidates stay in registers
-    Cand best;
+    Cand best = T;  // defined value: only read once bi >= 0
     int bi = -1;
     auto consider = [&](int idx, const Cand& c) {
       if (idx < 4 && haveT && ev_cmp(pts, c, T, zs) <= 0) return;
