@@ -94,25 +94,38 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
       break;
     }
-    // candidates: 0 next L event, 1 next R event, 2..5 bridge moves; the
-    // indices are compile-time constants so that the candidates stay in
-    // registers
-    Cand best = T;  // defined value: only read once bi >= 0
-    int bi = -1;
-    auto consider = [&](int idx, const Cand& c) {
-      if (haveT && ev_cmp(pts, c, T, zs) <= 0) return;
-      if (bi < 0 || ev_cmp(pts, c, best, zs) < 0) {
-        best = c;
-        bi = idx;
-      }
-    };
+    // candidates: 0 next L event, 1 next R event, 2..5 bridge moves.  The
+    // running best is kept field by field in scalars, every candidate index
+    // is a compile-time constant: the candidates stay in registers.
+    int bi = -1, ba = 0, bw = 0, bb = 0, bk = 0;
+    double bs = 0.0;
+#define HULL_CONSIDER(IDX, CAND)                                                  \
+  do {                                                                            \
+    const Cand cc_ = (CAND);                                                      \
+    bool take_ = !(haveT && ev_cmp(pts, cc_, T, zs) <= 0);                        \
+    if (take_ && bi >= 0) {                                                       \
+      Cand cb_;                                                                   \
+      cb_.t = Tri{ba, bw, bb};                                                    \
+      cb_.st = bs;                                                                \
+      cb_.kind = bk;                                                              \
+      take_ = ev_cmp(pts, cc_, cb_, zs) < 0;                                      \
+    }                                                                             \
+    if (take_) {                                                                  \
+      bi = (IDX);                                                                 \
+      ba = cc_.t.a;                                                               \
+      bw = cc_.t.w;                                                               \
+      bb = cc_.t.b;                                                               \
+      bs = cc_.st;                                                                \
+      bk = cc_.kind;                                                              \
+    }                                                                             \
+  } while (0)
     if (i < nL) {
       Event E = Lev[i];
       Cand c;
       c.t = Tri{E.a, E.w, E.b};
       c.kind = E.kind;
       c.st = Ltau[i];
-      consider(0, c);
+      HULL_CONSIDER(0, c);
     }
     if (j < nR) {
       Event E = Rev[j];
@@ -120,15 +133,18 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       c.t = Tri{E.a, E.w, E.b};
       c.kind = E.kind;
       c.st = Rtau[j];
-      consider(1, c);
+      HULL_CONSIDER(1, c);
     }
     const int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
-    if (nu != kNil) consider(2, make_cand(pts, u, nu, v, Pu, pts[nu], Pv, 1, zs));
-    if (pu != kNil) consider(3, make_cand(pts, pu, u, v, pts[pu], Pu, Pv, 0, zs));
-    if (pvv != kNil) consider(4, make_cand(pts, u, pvv, v, Pu, pts[pvv], Pv, 1, zs));
-    if (nv != kNil) consider(5, make_cand(pts, u, v, nv, Pu, Pv, pts[nv], 0, zs));
+    if (nu != kNil) HULL_CONSIDER(2, make_cand(pts, u, nu, v, Pu, pts[nu], Pv, 1, zs));
+    if (pu != kNil) HULL_CONSIDER(3, make_cand(pts, pu, u, v, pts[pu], Pu, Pv, 0, zs));
+    if (pvv != kNil) HULL_CONSIDER(4, make_cand(pts, u, pvv, v, Pu, pts[pvv], Pv, 1, zs));
+    if (nv != kNil) HULL_CONSIDER(5, make_cand(pts, u, v, nv, Pu, Pv, pts[nv], 0, zs));
+#undef HULL_CONSIDER
     if (bi < 0) break;
-    T = best;
+    T.t = Tri{ba, bw, bb};
+    T.st = bs;
+    T.kind = bk;
     haveT = true;
     bool emit = false;
     if (bi <= 1) {

@@ -272,25 +272,44 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
       break;
     }
     // candidates: 0..3 bridge moves (checked against T), 4..7 the next link
-    // changes of u and v (after T by construction); all indices below are
-    // compile-time constants so that the candidates stay in registers
-    Cand best = T;  // defined value: only read once bi >= 0
-    int bi = -1;
-    auto consider = [&](int idx, const Cand& c) {
-      if (idx < 4 && haveT && ev_cmp(pts, c, T, zs) <= 0) return;
-      if (bi < 0 || ev_cmp(pts, c, best, zs) < 0) {
-        best = c;
-        bi = idx;
-      }
-    };
-    if (U.nx != kNil) consider(0, make_cand(pts, U.p, U.nx, V.p, Pu, pts[U.nx], Pv, 1, zs));
-    if (U.pv != kNil) consider(1, make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs));
-    if (V.pv != kNil) consider(2, make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs));
-    if (V.nx != kNil) consider(3, make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs));
-    if (U.cr < U.nR) consider(4, cand_entry(R.entR, R.entRt, U.oR + U.cr));
-    if (U.cl < U.nL) consider(5, cand_entry(R.entL, R.entLt, U.oL + U.cl));
-    if (V.cl < V.nL) consider(6, cand_entry(R.entL, R.entLt, V.oL + V.cl));
-    if (V.cr < V.nR) consider(7, cand_entry(R.entR, R.entRt, V.oR + V.cr));
+    // changes of u and v (after T by construction).  The running best is
+    // kept field by field in scalars and every candidate index is a
+    // compile-time constant, so the candidates stay in registers.
+    int bi = -1, ba = 0, bw = 0, bb = 0, bk = 0;
+    double bs = 0.0;
+#define HULL_CONSIDER(IDX, CAND)                                                  \
+  do {                                                                            \
+    const Cand cc_ = (CAND);                                                      \
+    bool take_ = !((IDX) < 4 && haveT && ev_cmp(pts, cc_, T, zs) <= 0);           \
+    if (take_ && bi >= 0) {                                                       \
+      Cand cb_;                                                                   \
+      cb_.t = Tri{ba, bw, bb};                                                    \
+      cb_.st = bs;                                                                \
+      cb_.kind = bk;                                                              \
+      take_ = ev_cmp(pts, cc_, cb_, zs) < 0;                                      \
+    }                                                                             \
+    if (take_) {                                                                  \
+      bi = (IDX);                                                                 \
+      ba = cc_.t.a;                                                               \
+      bw = cc_.t.w;                                                               \
+      bb = cc_.t.b;                                                               \
+      bs = cc_.st;                                                                \
+      bk = cc_.kind;                                                              \
+    }                                                                             \
+  } while (0)
+    if (U.nx != kNil) HULL_CONSIDER(0, make_cand(pts, U.p, U.nx, V.p, Pu, pts[U.nx], Pv, 1, zs));
+    if (U.pv != kNil) HULL_CONSIDER(1, make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs));
+    if (V.pv != kNil) HULL_CONSIDER(2, make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs));
+    if (V.nx != kNil) HULL_CONSIDER(3, make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs));
+    if (U.cr < U.nR) HULL_CONSIDER(4, cand_entry(R.entR, R.entRt, U.oR + U.cr));
+    if (U.cl < U.nL) HULL_CONSIDER(5, cand_entry(R.entL, R.entLt, U.oL + U.cl));
+    if (V.cl < V.nL) HULL_CONSIDER(6, cand_entry(R.entL, R.entLt, V.oL + V.cl));
+    if (V.cr < V.nR) HULL_CONSIDER(7, cand_entry(R.entR, R.entRt, V.oR + V.cr));
+#undef HULL_CONSIDER
+    Cand best;
+    best.t = Tri{ba, bw, bb};
+    best.st = bs;
+    best.kind = bk;
     if (bi < 0) break;
     if (haveEnd && ev_cmp(pts, best, Tend, zs) > 0) break;
     T = best;
