@@ -57,6 +57,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   for (int guard = 0;; ++guard) {
     if (guard > 2 * (e - s) + 4) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
+      R.len_out[s] = 0;
       return;
     }
     int w = R.nx0[v];
@@ -199,6 +200,88 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
   merge_one(A.run[r], A.h, s, m, e);
 }
 
+// Bottom levels fused in LDS: one workgroup takes a tile of 2^KT consecutive
+// ranks (run blockIdx.y) through merge levels 1..KT with the lane-serial
+// merge, every array of the tile (points, links, both movie buffers) in LDS.
+// Only the tile's final movie and -inf links go back to HBM, in the layout
+// the level loop expects after KT levels (block start = tile start).
+template <int KT>
+__global__ void __launch_bounds__(256) k_merge_tile(LevelArgs A, const int4* __restrict__ gpts,
+                                                    int outbuf_is_b) {
+  constexpr int TP = 1 << KT;
+  __shared__ int4 P[TP];
+  __shared__ int pv0[TP], nx0[TP], pv[TP], nx[TP];
+  __shared__ Event ev[2][2 * TP];
+  __shared__ double tau[2][2 * TP];
+  __shared__ int len[2][TP];
+  const RunPtrs& G = A.run[blockIdx.y];
+  if (!G.pts) return;
+  const int64_t base = (int64_t)blockIdx.x * TP;
+  const int tn = (int)std::min<int64_t>(TP, A.n - base);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < TP; i += nt) {
+    if (i < tn) P[i] = gpts[base + i];
+    pv0[i] = kNil;
+    nx0[i] = kNil;
+    len[0][i] = 0;
+  }
+  __syncthreads();
+  RunPtrs R = G;
+  R.pts = P;
+  R.pv0 = pv0;
+  R.nx0 = nx0;
+  R.pv = pv;
+  R.nx = nx;
+  int buf = 0;
+  for (int k = 1; k <= KT; ++k) {
+    const int width = 1 << k, half = width >> 1;
+    for (int i = tid; i < tn; i += nt) {
+      pv[i] = pv0[i];
+      nx[i] = nx0[i];
+    }
+    __syncthreads();
+    R.ev_in = ev[buf];
+    R.tau_in = tau[buf];
+    R.len_in = len[buf];
+    R.ev_out = ev[buf ^ 1];
+    R.tau_out = tau[buf ^ 1];
+    R.len_out = len[buf ^ 1];
+    const int blocks = (tn + width - 1) / width;
+    for (int b = tid; b < blocks; b += nt) {
+      const int s = b * width, m = s + half, e = std::min(s + width, tn);
+      if (m >= e) {  // unpaired trailing block: passes through
+        int L = R.len_in[s];
+        for (int q = 0; q < L; ++q) {
+          R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
+          R.tau_out[2 * s + q] = R.tau_in[2 * s + q];
+        }
+        R.len_out[s] = L;
+      } else if (A.h->err) {
+        R.len_out[s] = 0;
+      } else {
+        merge_one(R, A.h, s, m, e);
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // the tile is one block now: its movie, lengths and -inf links to HBM
+  const int L = len[buf][0];
+  Event* gev = G.ev_out + 2 * base;
+  double* gtau = G.tau_out + 2 * base;
+  (void)outbuf_is_b;
+  for (int q = tid; q < L; q += nt) {
+    Event E = ev[buf][q];
+    gev[q] = Event{E.a + (int)base, E.w + (int)base, E.b + (int)base, E.kind};
+    gtau[q] = tau[buf][q];
+  }
+  for (int i = tid; i < tn; i += nt) {
+    G.pv0[base + i] = pv0[i] == kNil ? kNil : pv0[i] + (int)base;
+    G.nx0[base + i] = nx0[i] == kNil ? kNil : nx0[i] + (int)base;
+  }
+  if (tid == 0) G.len_out[base] = L;
+}
+
 // The unpaired trailing block of a level keeps its movie: copy it across.
 __global__ void __launch_bounds__(256) k_passthrough(LevelArgs A, int64_t s) {
   int r = blockIdx.y;
@@ -316,6 +399,15 @@ static int serial_levels() {
   return 12;
 }
 
+// Levels fused in LDS at the bottom (7, 8 or 9; 0 = none).  Tunable through
+// HULL_FUSED_LEVELS.
+static int fused_levels() {
+  const char* e = getenv("HULL_FUSED_LEVELS");
+  int v = (e && *e) ? atoi(e) : 8;
+  if (v <= 0) return 0;
+  return v < 7 ? 7 : (v > 9 ? 9 : v);
+}
+
 // Child events per time segment of a bridge walk (parallel strategy).
 // Tunable through HULL_WALK_SEGMENT.
 static int seg_events() {
@@ -379,7 +471,30 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
   }
   int32_t* partials = (int32_t*)(ws + pl.partials);
   int buf = 0;
-  for (int k = 1; k <= levels; ++k) {
+  // levels 1..KT fused in LDS, one workgroup per tile of 2^KT ranks
+  int KT = std::min(fused_levels(), levels);
+  if (KT > 0) {
+    for (int r = 0; r < 2; ++r) {
+      RunPtrs& R = A.run[r];
+      R.ev_out = (Event*)(ws + pl.ev[r][KT & 1]);
+      R.tau_out = (double*)(ws + pl.tau[r][KT & 1]);
+      R.len_out = (int*)(ws + pl.len[r][KT & 1]);
+    }
+    if (events) (void)hipEventRecord(events[2], s);
+    const int64_t tiles = (n + (int64_t(1) << KT) - 1) >> KT;
+    const int4* gpts = (const int4*)(ws + pl.pts);
+    if (KT == 8)
+      hipLaunchKernelGGL(k_merge_tile<8>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
+    else if (KT == 9)
+      hipLaunchKernelGGL(k_merge_tile<9>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
+    else
+      hipLaunchKernelGGL(k_merge_tile<7>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
+    if (events)
+      for (int q = 3; q <= 2 * KT + 1; ++q) (void)hipEventRecord(events[q], s);
+    HULL_LAUNCH_CHECK();
+    buf = KT & 1;
+  }
+  for (int k = KT + 1; k <= levels; ++k) {
     A.width = int64_t(1) << k;
     A.half = A.width >> 1;
     int64_t blocks = (n + A.width - 1) / A.width;
