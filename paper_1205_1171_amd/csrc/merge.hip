@@ -472,7 +472,9 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
   int32_t* partials = (int32_t*)(ws + pl.partials);
   int buf = 0;
   // levels 1..KT fused in LDS, one workgroup per tile of 2^KT ranks
-  int KT = std::min(fused_levels(), levels);
+  // (only when at least KT levels are asked for: the kernel runs exactly KT)
+  int KT = fused_levels();
+  if (KT > levels) KT = 0;
   if (KT > 0) {
     for (int r = 0; r < 2; ++r) {
       RunPtrs& R = A.run[r];
@@ -483,12 +485,12 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     if (events) (void)hipEventRecord(events[2], s);
     const int64_t tiles = (n + (int64_t(1) << KT) - 1) >> KT;
     const int4* gpts = (const int4*)(ws + pl.pts);
-    if (KT == 8)
-      hipLaunchKernelGGL(k_merge_tile<8>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
-    else if (KT == 9)
-      hipLaunchKernelGGL(k_merge_tile<9>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
-    else
+    if (KT == 7)
       hipLaunchKernelGGL(k_merge_tile<7>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
+    else if (KT == 8)
+      hipLaunchKernelGGL(k_merge_tile<8>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
+    else
+      hipLaunchKernelGGL(k_merge_tile<9>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
     if (events)
       for (int q = 3; q <= 2 * KT + 1; ++q) (void)hipEventRecord(events[q], s);
     HULL_LAUNCH_CHECK();
