@@ -403,7 +403,7 @@ static int serial_levels() {
 // HULL_FUSED_LEVELS.
 static int fused_levels() {
   const char* e = getenv("HULL_FUSED_LEVELS");
-  int v = (e && *e) ? atoi(e) : 8;
+  int v = (e && *e) ? atoi(e) : 0;
   if (v <= 0) return 0;
   return v < 7 ? 7 : (v > 9 ? 9 : v);
 }
@@ -412,7 +412,7 @@ static int fused_levels() {
 // Tunable through HULL_WALK_SEGMENT.
 static int seg_events() {
   const char* e = getenv("HULL_WALK_SEGMENT");
-  int v = (e && *e) ? atoi(e) : 2048;
+  int v = (e && *e) ? atoi(e) : 128;
   return v < 8 ? 8 : v;
 }
 
