@@ -50,11 +50,53 @@ __device__ __noinline__ int tri_cmp_exact(const int4* pts, Tri A, Tri B, int zs)
   return 0;
 }
 
+// Leading terms of D and N of a triple, exact in int64: D0, N0 (the
+// unperturbed orientations) and D1, N1 (their e1 coefficients).
+struct Lead {
+  int64_t d0, n0, d1, n1;
+};
+
+__device__ __forceinline__ Lead lead_of(int4 P, int4 Q, int4 R, int zs) {
+  int64_t dx1 = (int64_t)Q.x - P.x, dx2 = (int64_t)R.x - P.x;
+  int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
+  int64_t dz1 = (int64_t)Q.z - P.z, dz2 = (int64_t)R.z - P.z;
+  int64_t di1 = (int64_t)Q.w - P.w, di2 = (int64_t)R.w - P.w;
+  Lead L;
+  L.d0 = dx1 * dy2 - dx2 * dy1;
+  L.n0 = zs * (dx1 * dz2 - dx2 * dz1);
+  L.d1 = di1 * dy2 - di2 * dy1;
+  L.n1 = zs * (di1 * dz2 - di2 * dz1);
+  return L;
+}
+
+// Exact order when the double filter cannot decide.  The first three
+// coefficients of N_A D_B - N_B D_A (monomials 1, e1, e1^2) fit int128:
+//   N0a D0b - N0b D0a,  N0a D1b + N1a D0b - N0b D1a - N1b D0a,  N1a D1b - N1b D1a.
+// They decide every tie of the standard parts that comes from a pair of
+// points with equal x (all triples on such a pair share a standard part),
+// with no 256-bit arithmetic; only when all three vanish (or D0 = D1 = 0)
+// does the full cascade run.
+__device__ __noinline__ int tri_cmp_mid(const int4* pts, Tri A, Tri B, int zs) {
+  Lead a = lead_of(pts[A.a], pts[A.w], pts[A.b], zs);
+  Lead b = lead_of(pts[B.a], pts[B.w], pts[B.b], zs);
+  int sa = a.d0 ? (a.d0 > 0 ? 1 : -1) : (a.d1 > 0) - (a.d1 < 0);
+  int sb = b.d0 ? (b.d0 > 0 ? 1 : -1) : (b.d1 > 0) - (b.d1 < 0);
+  if (sa && sb) {
+    i128 p = (i128)a.n0 * b.d0 - (i128)b.n0 * a.d0;
+    if (!p) {
+      p = (i128)a.n0 * b.d1 + (i128)a.n1 * b.d0 - (i128)b.n0 * a.d1 - (i128)b.n1 * a.d0;
+      if (!p) p = (i128)a.n1 * b.d1 - (i128)b.n1 * a.d1;
+    }
+    if (p) return (p > 0 ? 1 : -1) * sa * sb;
+  }
+  return tri_cmp_exact(pts, A, B, zs);
+}
+
 __device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand& B, int zs) {
   if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
   int s = std_cmp(A.st, B.st);
   if (s) return s;
-  return tri_cmp_exact(pts, A.t, B.t, zs);
+  return tri_cmp_mid(pts, A.t, B.t, zs);
 }
 
 // Perturbed sign of D when D0 = D1 = 0 (cold path).
