@@ -96,6 +96,35 @@ int32_t hull_movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level,
                     int32_t* d_block_len, int32_t* d_order, int64_t* d_info, void* d_ws,
                     size_t ws_bytes, void* stream);
 
+/* Volume and surface area of H closed hull surfaces (FP32), for clouds given
+ * as float positions:
+ *   d_p        device float [N, 3]; cloud h is rows [pt_off[h], pt_off[h+1])
+ *   d_pt_off   device int64 [H + 1]
+ *   d_faces    device int32 [F, 3]: outward faces, indices local to the cloud
+ *              (as hull_full returns them); cloud h owns face rows
+ *              [face_off[h], face_off[h+1])
+ *   d_face_off device int64 [H + 1]
+ *   d_V, d_A   device float [H] (written)
+ * V = 1/6 sum_f (a - c).((b - c) x (d - c)) with c = the cloud's point 0,
+ * A = 1/2 sum_f |(b - a) x (d - a)|; per-face FP32 terms, compensated
+ * per-thread sums and a fixed-order tree reduction (deterministic).  One
+ * workgroup per cloud. */
+int32_t hull_volume_area_fwd(const float* d_p, const int64_t* d_pt_off, const int32_t* d_faces,
+                             const int64_t* d_face_off, int32_t H, float* d_V, float* d_A,
+                             void* stream);
+
+/* Gradient of sum_h (gV[h] V_h + gA[h] A_h) with respect to the positions,
+ * on the fixed face set (faces carry no gradient):
+ *   dV/dp = 1/6 sum of the face normals (b - a) x (d - a) around p,
+ *   dA/da = 1/2 (b - d) x unit normal, summed over the faces (a, b, d) at a
+ *           (0 for zero-area faces).
+ * d_gV / d_gA: device float [H] (either may be NULL = 0); d_grad_p: device
+ * float [N, 3], fully overwritten.  Contributions are added with float
+ * atomics, so the last bits may depend on the execution order. */
+int32_t hull_volume_area_bwd(const float* d_p, const int64_t* d_pt_off, const int32_t* d_faces,
+                             const int64_t* d_face_off, int32_t H, const float* d_gV,
+                             const float* d_gA, float* d_grad_p, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

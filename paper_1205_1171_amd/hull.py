@@ -54,6 +54,10 @@ def lib():
     L.hull_full_timed.restype = i32
     L.hull_movies.argtypes = [P, i64, i32, i32, P, P, P, P, P, sz, P]
     L.hull_movies.restype = i32
+    L.hull_volume_area_fwd.argtypes = [P, P, P, P, i32, P, P, P]
+    L.hull_volume_area_fwd.restype = i32
+    L.hull_volume_area_bwd.argtypes = [P, P, P, P, i32, P, P, P, P]
+    L.hull_volume_area_bwd.restype = i32
     _lib = L
     return L
 
@@ -62,7 +66,7 @@ def exported_symbols():
     """Names declared in include/hull3d.h that the library exports."""
     L = lib()
     names = ["hull_strerror", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
-             "hull_movies"]
+             "hull_movies", "hull_volume_area_fwd", "hull_volume_area_bwd"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -159,3 +163,32 @@ def movies(xyz, run, level, ws=None):
     if st:
         raise HullError(st, "device")
     return ev.cpu().numpy(), bl.cpu().numpy(), order.cpu().numpy()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def volume_area_fwd(p, pt_off, faces, face_off, stream=None):
+    """(V, A) per cloud, float32 device tensors [H]."""
+    import torch
+    H = pt_off.numel() - 1
+    V = torch.empty(H, dtype=torch.float32, device=p.device)
+    A = torch.empty(H, dtype=torch.float32, device=p.device)
+    rc = lib().hull_volume_area_fwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
+                                    _ptr(V), _ptr(A), _stream(stream))
+    if rc:
+        raise HullError(rc, "hull_volume_area_fwd")
+    return V, A
+
+
+def volume_area_bwd(p, pt_off, faces, face_off, gV, gA, stream=None):
+    """Gradient [N, 3] of sum(gV * V + gA * A) with respect to p."""
+    import torch
+    H = pt_off.numel() - 1
+    g = torch.empty_like(p)
+    rc = lib().hull_volume_area_bwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
+                                    _ptr(gV), _ptr(gA), _ptr(g), _stream(stream))
+    if rc:
+        raise HullError(rc, "hull_volume_area_bwd")
+    return g

@@ -70,3 +70,15 @@ def test_argument_errors_are_synchronous(L):
         assert fn(fake, (1 << 26) + 1, fake, 1 << 28, info, fake, 1 << 40, None) == hull.HULL_EINVAL
     assert L.hull_movies(fake, 100, 2, 1, fake, fake, fake, info, fake, ws, None) == hull.HULL_EINVAL
     assert L.hull_movies(fake, 0, 0, 1, fake, fake, fake, info, fake, ws, None) == hull.HULL_EINVAL
+
+
+def test_volume_area_argument_errors(L):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    assert L.hull_volume_area_fwd(fake, fake, fake, fake, -1, fake, fake, None) == hull.HULL_EINVAL
+    assert L.hull_volume_area_fwd(None, fake, fake, fake, 2, fake, fake, None) == hull.HULL_EINVAL
+    assert L.hull_volume_area_fwd(fake, fake, fake, fake, 2, None, fake, None) == hull.HULL_EINVAL
+    assert L.hull_volume_area_fwd(None, None, None, None, 0, None, None, None) == hull.HULL_OK
+    assert L.hull_volume_area_bwd(fake, fake, fake, fake, -3, fake, fake, fake, None) == hull.HULL_EINVAL
+    assert L.hull_volume_area_bwd(fake, fake, None, fake, 2, fake, fake, fake, None) == hull.HULL_EINVAL
+    assert L.hull_volume_area_bwd(fake, fake, fake, fake, 2, fake, fake, None, None) == hull.HULL_EINVAL
