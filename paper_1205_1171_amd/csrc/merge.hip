@@ -396,7 +396,7 @@ static unsigned grid_for(int64_t work, int64_t cap_blocks = 4096) {
 static int serial_levels() {
   const char* e = getenv("HULL_SERIAL_LEVELS");
   if (e && *e) return atoi(e);
-  return 12;
+  return 10;
 }
 
 // Levels fused in LDS at the bottom (7, 8 or 9; 0 = none).  Tunable through
@@ -412,7 +412,7 @@ static int fused_levels() {
 // Tunable through HULL_WALK_SEGMENT.
 static int seg_events() {
   const char* e = getenv("HULL_WALK_SEGMENT");
-  int v = (e && *e) ? atoi(e) : 128;
+  int v = (e && *e) ? atoi(e) : 16;
   return v < 8 ? 8 : v;
 }
 
