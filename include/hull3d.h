@@ -84,6 +84,46 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
                         int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream,
                         void* const* events, int32_t nevents);
 
+/* Merge schedule of a batched call (every field < 0, or 0 for walk_segment,
+ * takes the library default):
+ *   serial_levels  merge levels 1..serial_levels run one lane per merge (the
+ *                  paper's kernel, Sec. 3); the levels above split each merge
+ *                  into time segments walked in parallel (default 10)
+ *   walk_segment   child events per walk segment, >= 8 (default 16)
+ *   fused_levels   0, or 7..9: the bottom levels of a single hull merged in
+ *                  LDS tiles of 2^fused_levels points (default 0) */
+typedef struct hull_schedule_t {
+  int32_t serial_levels;
+  int32_t walk_segment;
+  int32_t fused_levels;
+  int32_t reserved;
+} hull_schedule_t;
+
+/* Bytes of device workspace for hull_full_batched over H hulls of
+ * total_points points in all (host, synchronous). */
+int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* bytes);
+
+/* Full hulls of H independent point clouds in one launch sequence: every
+ * merge level of every hull runs in the same kernels (the level loop of
+ * Sec. 3 over a device-built list of the merges of all hulls).
+ *   d_xyz          device int32 [N, 3], N = h_offsets[H]; cloud h is rows
+ *                  [offsets[h], offsets[h+1]), each of at most 2^26 points
+ *   d_offsets      device int64 [H + 1], offsets[0] = 0, non-decreasing
+ *   h_offsets      host copy of the same offsets (read during the call)
+ *   d_faces        device int32 [cap, 3], cap >= 2N (written): the faces of
+ *                  cloud h are rows [face_offsets[h], face_offsets[h+1]),
+ *                  lower then upper, indices local to the cloud; a cloud
+ *                  of fewer than 3 points has none
+ *   d_face_offsets device int64 [H + 1] (written)
+ *   d_info         device int64 [2]: status, total faces (written)
+ *   schedule       NULL = defaults
+ * The perturbation index of a point is its index within its own cloud, so
+ * each cloud's faces equal those of hull_full on that cloud alone. */
+int32_t hull_full_batched(const int32_t* d_xyz, const int64_t* d_offsets, const int64_t* h_offsets,
+                          int64_t H, int32_t* d_faces, int64_t cap, int64_t* d_face_offsets,
+                          int64_t* d_info, void* d_ws, size_t ws_bytes,
+                          const hull_schedule_t* schedule, void* stream);
+
 /* Intermediate movies, for inspection and tests: sorts, runs `level` merge
  * levels (level < 0: all) of run 0 (lower) or 1 (upper) and writes, for
  * every block of width 2^level from rank 0, its movie events at offset

@@ -9,7 +9,8 @@
 namespace hull {
 
 constexpr int kNil = -1;
-constexpr int64_t kMaxN = int64_t(1) << 26;
+constexpr int64_t kMaxN = int64_t(1) << 26;      // points of one hull
+constexpr int64_t kMaxTotal = int64_t(1) << 29;  // points of a batch
 constexpr int32_t kMaxCoord = 1 << 29;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
@@ -18,6 +19,7 @@ constexpr int kRadixBits = 8;
 constexpr int kBuckets = 1 << kRadixBits;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
+constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
 
 // Device-side status words at the head of every workspace.
 struct Header {
@@ -35,22 +37,27 @@ struct Event {
   int a, w, b, kind;
 };
 
-// Offsets (bytes) of every workspace region for a single hull of n points.
+// Offsets (bytes) of every workspace region for n points in H hulls.
 struct Plan {
-  size_t header, keys0, vals0, keys1, vals1, counts, partials, pts;
+  size_t header, keys0, vals0, keys1, vals1, counts, partials, pts, hid, off1;
   size_t pv0[2], nx0[2], pv[2], nx[2];
   size_t ev[2][2], tau[2][2], len[2][2];  // [run][buffer]
+  // the level schedule (merge list, trailing blocks)
+  size_t mcnt, moff, tcnt, toff, tlist, mlist;
   // parallel merge strategy, per run
-  size_t cntR[2], cntL[2], offR[2], offL[2], curR[2], curL[2], entR[2], entL[2];
-  size_t entRt[2], entLt[2], segS[2], segBase[2], segMerge[2], segCnt[2], segOff[2];
-  size_t bev[2], btau[2], buv[2], nB[2], uv0[2], surv[2], jb[2], pre[2];
+  size_t cntR[2], cntL[2], offR[2], offL[2], curR[2], curL[2], claimR[2], claimL[2];
+  size_t entR[2], entL[2], entRt[2], entLt[2], ctr[2], touched[2];
+  size_t ecnt[2], eoff[2], cslot[2], cmerge[2];
+  size_t segS[2], segBase[2], segMerge[2], segCnt[2], segOff[2];
+  size_t bev[2], btau[2], buv[2], nB[2], boff[2], uv0[2], surv[2], jb[2], pre[2];
+  // face counts of the hulls of a batch
+  size_t fcnt;
   size_t total;
-  int64_t n, tiles, count_len, partial_len;
+  int64_t n, H, tiles, count_len, partial_len, mcap, seg_cap;
 };
 
-Plan make_plan(int64_t n);
-
-inline int32_t hip_status(hipError_t e) { return e == hipSuccess ? HULL_OK : HULL_EHIP; }
+// min_seg: the smallest walk segment (child events) the plan must hold.
+Plan make_plan(int64_t n, int64_t H, int min_seg = 8);
 
 #define HULL_LAUNCH_CHECK()                         \
   do {                                              \
@@ -61,16 +68,17 @@ inline int32_t hip_status(hipError_t e) { return e == hipSuccess ? HULL_OK : HUL
 // Clear the device status words (a kernel, so that the call can be captured).
 void init_header(Header* h, hipStream_t s);
 
-// Sort: ranks by (x, input index).  Fills pts (int4 x, y, z, i by rank).
-int32_t sort_points(const int32_t* d_xyz, int64_t n, char* ws, const Plan& pl, hipStream_t s);
+// Sort: ranks by (hull, x, index within the hull).  Fills pts (int4 x, y, z,
+// index within the hull, by rank).  hull_off (device [H + 1]) may be NULL for
+// a single hull.
+int32_t sort_points(const int32_t* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
+                    const Plan& pl, hipStream_t s);
 
-// Exclusive scan of int32 counts (device, in place into `out`).
+// Exclusive scans of int32 (in place allowed).  The second form reads its
+// length from device memory: len = *d_len + add, never more than cap.
 int32_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t len, int32_t* partials,
                            hipStream_t s);
-
-// Runs for one hull: lower (run 0) and/or upper (run 1).
-int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
-                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
-                  void* const* events, int32_t nevents);
+int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
+                           int64_t cap, int32_t* partials, hipStream_t s);
 
 }  // namespace hull

@@ -27,15 +27,27 @@ struct RunPtrs {
   int zs;
 };
 
+// The hulls of a call (rank offsets) and the level schedule built for every
+// level on the device: the merges (pairs of adjacent blocks inside a hull)
+// and the unpaired trailing blocks that are copied across.
+struct Sched {
+  const int64_t* off;  // [H + 1] rank offsets of the hulls
+  int64_t H;
+  int* moff;           // [H + 1] merges before each hull; moff[H] = merges of the level
+  int2* mlist;         // [mcap] (s, e) of each merge, m = s + half
+  int* toff;           // [H + 1] trailing blocks before each hull; toff[H] = their count
+  int* tlist;          // [H] trailing block starts
+  int64_t mcap;
+};
+
 struct LevelArgs {
   RunPtrs run[2];
   Header* h;
+  Sched S;
   int64_t n;
   int64_t half;   // size of a left block
   int64_t width;  // size of a merged block
-  int64_t merges; // merges per run
 };
-
 // Exact (time, rank triple) order of two events (cold path).  Arguments
 // go by value so that callers keep their candidates in registers.
 __device__ __noinline__ int tri_cmp_exact(const int4* pts, Tri A, Tri B, int zs) {
@@ -125,6 +137,17 @@ __device__ __forceinline__ Cand make_cand(const int4* pts, int a, int w, int b, 
   return c;
 }
 
+// Largest i in [0, count) with off[i] <= x (off non-decreasing, off[0] <= x).
+__device__ __forceinline__ int find_owner(const int* off, int count, int64_t x) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ Cand cand_of(const Event* ev, const double* tau, int64_t q) {
   Event E = ev[q];
   Cand c;
@@ -135,6 +158,9 @@ __device__ __forceinline__ Cand cand_of(const Event* ev, const double* tau, int6
 }
 
 // Pointers of one run for the parallel (bridge walk and scatter) strategy.
+// Everything is sized by the events of the level, not by the points: child
+// events are enumerated into a compact list, and per-point lists exist only
+// for the points those events touch.
 struct ParRun {
   const int4* pts;
   int* pv0;
@@ -145,40 +171,51 @@ struct ParRun {
   Event* ev_out;
   double* tau_out;
   int* len_out;
-  int* cntR;  // per point: # child events changing nx(p)
-  int* cntL;  // per point: # child events changing pv(p)
-  int* offR;
+  int* cntR;      // per point: # child events changing nx(p)
+  int* cntL;      // per point: # child events changing pv(p)
+  int* offR;      // per point: start of its list
   int* offL;
   int* curR;
   int* curL;
-  Event* entR;    // link-change events grouped by point, time-sorted
+  int* claimR;    // per point: level that allocated its list
+  int* claimL;
+  int stamp;      // this level's claim stamp: lists of other points are empty
+  Event* entR;    // link-change events grouped by point, time-sorted (kind | slot << 1)
   double* entRt;  // their times
   Event* entL;
   double* entLt;
-  int* segS;      // per merge: # time segments of its bridge walk (merges + 1)
+  int* ctr;       // [0] R entries, [1] L entries, [2] touched lists; [4..7] level totals:
+                  // merges, child events, walk segments, bridge events
+  int* touched;   // (point << 1 | side) of every allocated list
+  int* ecnt;      // per merge: child events (mcap + 1)
+  int* eoff;      // exclusive scan of ecnt
+  int* cslot;     // per child event: its slot in the input movies
+  int* cmerge;    // per child event: its merge
+  int* segS;      // per merge: # time segments of its bridge walk
   int* segBase;   // exclusive scan of segS
   int* segMerge;  // per segment: its merge
   int* segCnt;    // per segment: # bridge events
   int* segOff;    // exclusive scan of segCnt
-  Event* bev;  // bridge events of merge s at [2s, 2s + nB[s])
+  Event* bev;     // bridge events of merge (s, e) at slots [2s, 2s + nB)
   double* btau;
-  int2* buv;   // (u, v) after each bridge event
-  int* nB;     // at merge start s
-  int2* uv0;   // (u0, v0): the bridge at -inf, at merge start s
-  int* surv;   // per input slot: survives into the merged movie (2n + 1)
-  int* jb;     // per input slot: # bridge events before it
-  int* pre;    // exclusive scan of surv (2n + 1)
+  int2* buv;      // (u, v) after each bridge event
+  int* nB;        // per merge: # bridge events
+  int* boff;      // exclusive scan of nB
+  int2* uv0;      // per merge: the bridge at -inf
+  int* surv;      // per child event: survives into the merged movie (+1 entry)
+  int* jb;        // per child event: # bridge events before it
+  int* pre;       // exclusive scan of surv
   int zs;
 };
 
 struct ParLevel {
   ParRun run[2];
   Header* h;
-  int64_t n;
-  int k;           // level: input blocks of 2^(k-1) points, merged blocks of 2^k
-  int64_t merges;  // merges per run (an unpaired trailing block is not one)
-  int seg_events;  // child events per walk segment
-  int64_t seg_cap; // bound on the number of segments of the level
+  Sched S;
+  int k;            // level: input blocks of 2^(k-1) points, merged blocks of 2^k
+  int seg_events;   // child events per walk segment
+  int64_t seg_cap;  // bound on the walk segments of a level
+  int64_t ecap;     // bound on the child events of a level (2n)
 };
 
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s);

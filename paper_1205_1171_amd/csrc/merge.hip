@@ -185,19 +185,18 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
 }
 
 __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= 2 * A.merges) return;
-  int r = g >= A.merges ? 1 : 0;
-  int64_t q = g - r * A.merges;
-  if (!A.run[r].pts) return;
-  int64_t s = q * A.width, m = s + A.half, e = std::min(s + A.width, A.n);
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const RunPtrs& R = A.run[blockIdx.y];
+  if (!R.pts || g >= A.S.moff[A.S.H]) return;
+  const int2 se = A.S.mlist[g];
+  const int64_t s = se.x, m = s + A.half, e = se.y;
   // After an error the movies are empty, so that every later kernel still
   // reads lengths that were written.
   if (A.h->err) {
-    A.run[r].len_out[s] = 0;
+    R.len_out[s] = 0;
     return;
   }
-  merge_one(A.run[r], A.h, s, m, e);
+  merge_one(R, A.h, s, m, e);
 }
 
 // Bottom levels fused in LDS: one workgroup takes a tile of 2^KT consecutive
@@ -282,27 +281,33 @@ __global__ void __launch_bounds__(256) k_merge_tile(LevelArgs A, const int4* __r
   if (tid == 0) G.len_out[base] = L;
 }
 
-// The unpaired trailing block of a level keeps its movie: copy it across.
-__global__ void __launch_bounds__(256) k_passthrough(LevelArgs A, int64_t s) {
-  int r = blockIdx.y;
-  const RunPtrs& R = A.run[r];
+// The unpaired trailing block of a hull at this level keeps its movie: copy
+// it across (a hull already complete keeps its movie where it is).
+__global__ void __launch_bounds__(256) k_passthrough(LevelArgs A) {
+  const RunPtrs& R = A.run[blockIdx.y];
   if (!R.pts) return;
-  int len = R.len_in[s];
-  if (A.h->err || len < 0 || len > 2 * (A.n - s)) len = 0;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < len;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
-    R.tau_out[2 * s + q] = R.tau_in[2 * s + q];
+  const int count = A.S.toff[A.S.H];
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    const int64_t s = A.S.tlist[t];
+    int len = R.len_in[s];
+    if (A.h->err || len < 0 || len > 2 * A.half) len = 0;
+    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+      R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
+      R.tau_out[2 * s + q] = R.tau_in[2 * s + q];
+    }
+    if (threadIdx.x == 0) R.len_out[s] = len;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) R.len_out[s] = len;
 }
 
-__global__ void __launch_bounds__(256) k_init_links(int* pv0, int* nx0, int* len, int64_t n) {
+__global__ void __launch_bounds__(256) k_init_links(int* pv0, int* nx0, int* len, int* claimR,
+                                                    int* claimL, int64_t n) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     pv0[p] = kNil;
     nx0[p] = kNil;
     len[p] = 0;
+    claimR[p] = 0;
+    claimL[p] = 0;
   }
 }
 
@@ -317,30 +322,119 @@ __global__ void __launch_bounds__(256) k_copy_links(const int* __restrict__ pv0,
   }
 }
 
-// Faces from the final movies: event (a, w, b) gives the face with the
-// middle vertex w; an insertion has D(a, w, b) < 0, a deletion D > 0.  Lower
-// faces need D < 0 for an outward orientation, upper faces D > 0.
-__global__ void __launch_bounds__(256)
-    k_extract(const Event* __restrict__ evL, const int* lenL, const Event* __restrict__ evU,
-              const int* lenU, const int4* __restrict__ pts, int32_t* __restrict__ faces,
-              int64_t cap, int64_t* info, const Header* h) {
-  int nL = evL ? *lenL : 0, nU = evU ? *lenU : 0;
-  int64_t total = (int64_t)nL + nU;
-  const bool over = total > cap;
-  if (over || h->err) total = 0;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    bool lower = q < nL;
-    Event E = lower ? evL[q] : evU[q - nL];
-    bool keep = lower ? E.kind == 1 : E.kind == 0;
-    int a = pts[E.a].w, w = pts[E.w].w, b = pts[E.b].w;
-    faces[3 * q + 0] = a;
-    faces[3 * q + 1] = keep ? w : b;
-    faces[3 * q + 2] = keep ? b : w;
+__device__ __forceinline__ int dev_levels(int64_t n) {
+  int L = 0;
+  while ((int64_t(1) << L) < n) ++L;
+  return L;
+}
+
+// Level schedule: per hull, merges = floor(blocks / 2) and one trailing
+// block when the number of blocks is odd and above one.
+__global__ void __launch_bounds__(256) k_sched_count(Sched S, int k, int* mcnt, int* tcnt) {
+  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h <= S.H;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    if (h == S.H) {
+      mcnt[h] = 0;
+      tcnt[h] = 0;
+      continue;
+    }
+    const int64_t nh = S.off[h + 1] - S.off[h];
+    const int64_t w = int64_t(1) << (k - 1);
+    const int64_t nb = (nh + w - 1) >> (k - 1);
+    mcnt[h] = (int)(nb >> 1);
+    tcnt[h] = (nb > 1 && (nb & 1)) ? 1 : 0;
   }
+}
+
+__global__ void __launch_bounds__(256) k_sched_fill(Sched S, int k) {
+  const int merges = S.moff[S.H];
+  const int64_t width = int64_t(1) << k, w = width >> 1;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < merges;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int h = find_owner(S.moff, (int)S.H, g);
+    const int64_t s = S.off[h] + (g - S.moff[h]) * width;
+    const int64_t e = s + width < S.off[h + 1] ? s + width : S.off[h + 1];
+    S.mlist[g] = make_int2((int)s, (int)e);
+  }
+  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < S.H;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    if (S.toff[h + 1] > S.toff[h]) {
+      const int64_t nh = S.off[h + 1] - S.off[h];
+      const int64_t nb = (nh + w - 1) >> (k - 1);
+      S.tlist[S.toff[h]] = (int)(S.off[h] + (nb - 1) * w);
+    }
+  }
+}
+
+__global__ void k_set_off1(int64_t* off, int64_t n) {
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    off[1] = n;
+  }
+}
+
+// Faces: every hull's final movies sit in the buffer of its own last level.
+struct ExtractArgs {
+  Sched S;
+  const Event* ev[2][2];  // [run][buffer]
+  const int* len[2][2];
+  const int4* pts;
+  int* fcnt;  // [H + 1], scanned in place into face offsets
+  int32_t* faces;
+  int64_t cap;
+  int64_t* face_off;  // [H + 1] output (may be null)
+  int64_t* info;
+  const Header* h;
+};
+
+__global__ void __launch_bounds__(256) k_face_count(ExtractArgs X) {
+  const Sched& S = X.S;
+  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h <= S.H;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    int F = 0;
+    if (h < S.H) {
+      const int64_t o = S.off[h], nh = S.off[h + 1] - o;
+      if (nh >= 3) {
+        const int b = dev_levels(nh) & 1;
+        if (X.ev[0][b]) F += X.len[0][b][o];
+        if (X.ev[1][b]) F += X.len[1][b][o];
+      }
+    }
+    X.fcnt[h] = F;
+  }
+}
+
+// Event (a, w, b) gives the face with the middle vertex w; an insertion has
+// D(a, w, b) < 0, a deletion D > 0.  Lower faces need D < 0 for an outward
+// orientation, upper faces D > 0.  Indices are the points' own (within their
+// hull).
+__global__ void __launch_bounds__(256) k_extract(ExtractArgs X) {
+  const Sched& S = X.S;
+  const int64_t total = X.fcnt[S.H];
+  const bool over = total > X.cap || total < 0;
+  const int err = X.h->err;
+  const int64_t F = (over || err) ? 0 : total;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < F;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int h = find_owner(X.fcnt, (int)S.H, t);
+    const int64_t o = S.off[h];
+    const int b = dev_levels(S.off[h + 1] - o) & 1;
+    int64_t q = t - X.fcnt[h];
+    const int nl = X.ev[0][b] ? X.len[0][b][o] : 0;
+    const bool lower = q < nl;
+    const Event E = lower ? X.ev[0][b][2 * o + q] : X.ev[1][b][2 * o + (q - nl)];
+    const bool keep = lower ? E.kind == 1 : E.kind == 0;
+    const int a = X.pts[E.a].w, w = X.pts[E.w].w, c = X.pts[E.b].w;
+    X.faces[3 * t + 0] = a;
+    X.faces[3 * t + 1] = keep ? w : c;
+    X.faces[3 * t + 2] = keep ? c : w;
+  }
+  for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h <= S.H;
+       h += (int64_t)gridDim.x * blockDim.x)
+    if (X.face_off) X.face_off[h] = (over || err) ? 0 : X.fcnt[h];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    info[0] = h->err ? h->err : (over ? HULL_EINTERNAL : 0);
-    info[1] = total;
+    X.info[0] = err ? err : (over ? HULL_EINTERNAL : 0);
+    X.info[1] = F;
   }
 }
 
@@ -390,44 +484,52 @@ static unsigned grid_for(int64_t work, int64_t cap_blocks = 4096) {
   return (unsigned)b;
 }
 
-// Highest level merged by the lane-serial strategy; higher levels use the
-// parallel strategy.  Tunable through HULL_SERIAL_LEVELS (0 = parallel from
-// the first level, a large value = lane-serial throughout).
-static int serial_levels() {
-  const char* e = getenv("HULL_SERIAL_LEVELS");
-  if (e && *e) return atoi(e);
-  return 10;
+static int env_int(const char* name, int dflt) {
+  const char* e = getenv(name);
+  return (e && *e) ? atoi(e) : dflt;
 }
 
-// Levels fused in LDS at the bottom (7, 8 or 9; 0 = none).  Tunable through
-// HULL_FUSED_LEVELS.
-static int fused_levels() {
-  const char* e = getenv("HULL_FUSED_LEVELS");
-  int v = (e && *e) ? atoi(e) : 0;
-  if (v <= 0) return 0;
-  return v < 7 ? 7 : (v > 9 ? 9 : v);
+// The merge schedule: which levels run lane-serial, the walk segment length
+// and the LDS-fused bottom levels.  Unset fields take the environment
+// (HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT, HULL_FUSED_LEVELS), then defaults.
+struct Opts {
+  int serial_max, seg, fused;
+};
+
+static Opts resolve(const hull_schedule_t* sc) {
+  Opts o;
+  o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 10);
+  o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 16);
+  if (o.seg < 8) o.seg = 8;
+  o.fused = sc && sc->fused_levels >= 0 ? sc->fused_levels : env_int("HULL_FUSED_LEVELS", 0);
+  if (o.fused > 0) o.fused = o.fused < 7 ? 7 : (o.fused > 9 ? 9 : o.fused);
+  if (o.fused < 0) o.fused = 0;
+  return o;
 }
 
-// Child events per time segment of a bridge walk (parallel strategy).
-// Tunable through HULL_WALK_SEGMENT.
-static int seg_events() {
-  const char* e = getenv("HULL_WALK_SEGMENT");
-  int v = (e && *e) ? atoi(e) : 16;
-  return v < 8 ? 8 : v;
-}
-
-// Runs `levels` merge levels of the selected runs; returns the buffer index
-// holding the final movies.
-static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bool lower,
-                          bool upper, int levels, int* final_buf, hipEvent_t* events) {
+// Runs `levels` merge levels of the selected runs over the hulls of S.
+static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, hipStream_t s,
+                          bool lower, bool upper, int levels, const Opts& opt,
+                          hipEvent_t* events) {
   Header* h = (Header*)(ws + pl.header);
-  const int serial_max = serial_levels();
+  Sched S = S0;
+  S.moff = (int*)(ws + pl.moff);
+  S.mlist = (int2*)(ws + pl.mlist);
+  S.toff = (int*)(ws + pl.toff);
+  S.tlist = (int*)(ws + pl.tlist);
+  S.mcap = pl.mcap;
+  int* mcnt = (int*)(ws + pl.mcnt);
+  int* tcnt = (int*)(ws + pl.tcnt);
   LevelArgs A{};
   A.h = h;
+  A.S = S;
   A.n = n;
   ParLevel P{};
   P.h = h;
-  P.n = n;
+  P.S = S;
+  P.seg_events = opt.seg;
+  P.seg_cap = pl.seg_cap;
+  P.ecap = 2 * n;
   for (int r = 0; r < 2; ++r) {
     bool on = r == 0 ? lower : upper;
     RunPtrs& R = A.run[r];
@@ -448,10 +550,18 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     Q.offL = (int*)(ws + pl.offL[r]);
     Q.curR = (int*)(ws + pl.curR[r]);
     Q.curL = (int*)(ws + pl.curL[r]);
+    Q.claimR = (int*)(ws + pl.claimR[r]);
+    Q.claimL = (int*)(ws + pl.claimL[r]);
     Q.entR = (Event*)(ws + pl.entR[r]);
     Q.entL = (Event*)(ws + pl.entL[r]);
     Q.entRt = (double*)(ws + pl.entRt[r]);
     Q.entLt = (double*)(ws + pl.entLt[r]);
+    Q.ctr = (int*)(ws + pl.ctr[r]);
+    Q.touched = (int*)(ws + pl.touched[r]);
+    Q.ecnt = (int*)(ws + pl.ecnt[r]);
+    Q.eoff = (int*)(ws + pl.eoff[r]);
+    Q.cslot = (int*)(ws + pl.cslot[r]);
+    Q.cmerge = (int*)(ws + pl.cmerge[r]);
     Q.segS = (int*)(ws + pl.segS[r]);
     Q.segBase = (int*)(ws + pl.segBase[r]);
     Q.segMerge = (int*)(ws + pl.segMerge[r]);
@@ -461,20 +571,21 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     Q.btau = (double*)(ws + pl.btau[r]);
     Q.buv = (int2*)(ws + pl.buv[r]);
     Q.nB = (int*)(ws + pl.nB[r]);
+    Q.boff = (int*)(ws + pl.boff[r]);
     Q.uv0 = (int2*)(ws + pl.uv0[r]);
     Q.surv = (int*)(ws + pl.surv[r]);
     Q.jb = (int*)(ws + pl.jb[r]);
     Q.pre = (int*)(ws + pl.pre[r]);
     if (on)
       hipLaunchKernelGGL(k_init_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0,
-                         (int*)(ws + pl.len[r][0]), n);
+                         (int*)(ws + pl.len[r][0]), Q.claimR, Q.claimL, n);
   }
   int32_t* partials = (int32_t*)(ws + pl.partials);
   int buf = 0;
-  // levels 1..KT fused in LDS, one workgroup per tile of 2^KT ranks
-  // (only when at least KT levels are asked for: the kernel runs exactly KT)
-  int KT = fused_levels();
-  if (KT > levels) KT = 0;
+  // levels 1..KT fused in LDS, one workgroup per tile of 2^KT ranks (a single
+  // hull, and only when at least KT levels are asked for)
+  int KT = opt.fused;
+  if (KT > levels || S.H != 1) KT = 0;
   if (KT > 0) {
     for (int r = 0; r < 2; ++r) {
       RunPtrs& R = A.run[r];
@@ -496,14 +607,18 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
     HULL_LAUNCH_CHECK();
     buf = KT & 1;
   }
+  const unsigned hgrid = grid_for(S.H + 1, 1024);
   for (int k = KT + 1; k <= levels; ++k) {
     A.width = int64_t(1) << k;
     A.half = A.width >> 1;
-    int64_t blocks = (n + A.width - 1) / A.width;
-    int64_t last_s = (blocks - 1) * A.width;
-    bool trailing = last_s + A.half >= n;
-    A.merges = trailing ? blocks - 1 : blocks;
-    const bool serial = k <= serial_max;
+    const bool serial = k <= opt.serial_max;
+    // the schedule of this level
+    hipLaunchKernelGGL(k_sched_count, dim3(hgrid), dim3(256), 0, s, S, k, mcnt, tcnt);
+    int32_t rc = exclusive_scan_i32(mcnt, S.moff, S.H + 1, partials, s);
+    if (!rc) rc = exclusive_scan_i32(tcnt, S.toff, S.H + 1, partials, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sched_fill, dim3(grid_for(std::min<int64_t>(pl.mcap, n / A.width + S.H + 1))),
+                       dim3(256), 0, s, S, k);
     for (int r = 0; r < 2; ++r) {
       RunPtrs& R = A.run[r];
       R.ev_in = (const Event*)(ws + pl.ev[r][buf]);
@@ -524,28 +639,51 @@ static int32_t run_levels(int64_t n, char* ws, const Plan& pl, hipStream_t s, bo
                            R.nx, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
-    if (A.merges > 0) {
-      if (serial) {
-        hipLaunchKernelGGL(k_merge_level, dim3(grid_for(2 * A.merges, int64_t(1) << 30), 1),
-                           dim3(256), 0, s, A);
-      } else {
-        P.k = k;
-        P.merges = A.merges;
-        P.seg_events = seg_events();
-        // sum over merges of 1 + (events)/G, events <= 2 * (points)
-        P.seg_cap = std::min<int64_t>(A.merges + (2 * n) / P.seg_events + 1, n);
-        int32_t rc = parallel_level(P, partials, s);
-        if (rc) return rc;
-      }
+    if (serial) {
+      const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
+      hipLaunchKernelGGL(k_merge_level, dim3((unsigned)((bound + 255) / 256), 2), dim3(256), 0, s,
+                         A);
+    } else {
+      P.k = k;
+      P.run[0].stamp = P.run[1].stamp = k;
+      rc = parallel_level(P, partials, s);
+      if (rc) return rc;
     }
     if (events) (void)hipEventRecord(events[2 * k + 1], s);
-    if (trailing)
-      hipLaunchKernelGGL(k_passthrough, dim3(grid_for(2 * (n - last_s), 1024), 2), dim3(256), 0,
-                         s, A, last_s);
+    hipLaunchKernelGGL(k_passthrough, dim3((unsigned)std::min<int64_t>(S.H, 4096), 2), dim3(256),
+                       0, s, A);
     HULL_LAUNCH_CHECK();
     buf ^= 1;
   }
-  *final_buf = buf;
+  return HULL_OK;
+}
+
+// Faces of every hull of S after its merges.
+static int32_t extract(const Sched& S, char* ws, const Plan& pl, hipStream_t s, bool lower,
+                       bool upper, int32_t* d_faces, int64_t cap, int64_t* d_face_off,
+                       int64_t* d_info) {
+  ExtractArgs X{};
+  X.S = S;
+  for (int r = 0; r < 2; ++r)
+    for (int b = 0; b < 2; ++b) {
+      bool on = r == 0 ? lower : upper;
+      X.ev[r][b] = on ? (const Event*)(ws + pl.ev[r][b]) : nullptr;
+      X.len[r][b] = (const int*)(ws + pl.len[r][b]);
+    }
+  X.pts = (const int4*)(ws + pl.pts);
+  X.fcnt = (int*)(ws + pl.fcnt);
+  X.faces = d_faces;
+  X.cap = cap;
+  X.face_off = d_face_off;
+  X.info = d_info;
+  X.h = (const Header*)(ws + pl.header);
+  int32_t* partials = (int32_t*)(ws + pl.partials);
+  hipLaunchKernelGGL(k_face_count, dim3(grid_for(S.H + 1, 1024)), dim3(256), 0, s, X);
+  int32_t rc = exclusive_scan_i32(X.fcnt, X.fcnt, S.H + 1, partials, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_extract, dim3(grid_for(std::max<int64_t>(cap, S.H + 1), 2048)), dim3(256), 0,
+                     s, X);
+  HULL_LAUNCH_CHECK();
   return HULL_OK;
 }
 
@@ -557,7 +695,8 @@ int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap
   const int L = levels_for(n);
   if (events && nevents < 2 * L + 3) return HULL_EINVAL;
   hipEvent_t* ev = (hipEvent_t*)events;
-  Plan pl = make_plan(n);
+  const Opts opt = resolve(nullptr);
+  Plan pl = make_plan(n, 1, opt.seg);
   if (ws_bytes < pl.total) return HULL_EWORKSPACE;
   char* ws = (char*)d_ws;
   Header* h = (Header*)(ws + pl.header);
@@ -570,20 +709,56 @@ int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap
       for (int q = 1; q < 2 * L + 3; ++q) (void)hipEventRecord(ev[q], s);
     return HULL_OK;
   }
-  int32_t rc = sort_points(d_xyz, n, ws, pl, s);
+  int64_t* off = (int64_t*)(ws + pl.off1);
+  hipLaunchKernelGGL(k_set_off1, dim3(1), dim3(64), 0, s, off, n);
+  Sched S{};
+  S.off = off;
+  S.H = 1;
+  int32_t rc = sort_points(d_xyz, n, nullptr, 1, ws, pl, s);
   if (rc) return rc;
   if (ev) (void)hipEventRecord(ev[1], s);
-  int buf = 0;
-  rc = run_levels(n, ws, pl, s, lower, upper, L, &buf, ev);
+  rc = run_levels(n, S, ws, pl, s, lower, upper, L, opt, ev);
   if (rc) return rc;
-  const Event* evL = lower ? (const Event*)(ws + pl.ev[0][buf]) : nullptr;
-  const Event* evU = upper ? (const Event*)(ws + pl.ev[1][buf]) : nullptr;
-  hipLaunchKernelGGL(k_extract, dim3(grid_for(2 * n, 2048)), dim3(256), 0, s, evL,
-                     (const int*)(ws + pl.len[0][buf]), evU, (const int*)(ws + pl.len[1][buf]),
-                     (const int4*)(ws + pl.pts), d_faces, cap, d_info, h);
+  S.moff = (int*)(ws + pl.moff);
+  rc = extract(S, ws, pl, s, lower, upper, d_faces, cap, nullptr, d_info);
   if (ev) (void)hipEventRecord(ev[2 * L + 2], s);
-  HULL_LAUNCH_CHECK();
-  return HULL_OK;
+  return rc;
+}
+
+int32_t batched(const int32_t* d_xyz, const int64_t* d_off, const int64_t* h_off, int64_t H,
+                int32_t* d_faces, int64_t cap, int64_t* d_face_off, int64_t* d_info, void* d_ws,
+                size_t ws_bytes, const hull_schedule_t* sched, hipStream_t s) {
+  if (H < 1 || !d_off || !h_off || !d_info || !d_faces || !d_face_off || !d_ws) return HULL_EINVAL;
+  const int64_t n = h_off[H];
+  if (h_off[0] != 0 || n < 0 || n > kMaxTotal || (n > 0 && !d_xyz) || cap < 2 * n)
+    return HULL_EINVAL;
+  int L = 0;
+  for (int64_t q = 0; q < H; ++q) {
+    const int64_t nh = h_off[q + 1] - h_off[q];
+    if (nh < 0 || nh > kMaxN) return HULL_EINVAL;
+    L = std::max(L, levels_for(nh));
+  }
+  const Opts opt = resolve(sched);
+  Plan pl = make_plan(n, H, opt.seg);
+  if (ws_bytes < pl.total) return HULL_EWORKSPACE;
+  char* ws = (char*)d_ws;
+  Header* h = (Header*)(ws + pl.header);
+  init_header(h, s);
+  Sched S{};
+  S.off = d_off;
+  S.H = H;
+  if (n > 0) {
+    int32_t rc = sort_points(d_xyz, n, d_off, H, ws, pl, s);
+    if (rc) return rc;
+    rc = run_levels(n, S, ws, pl, s, true, true, L, opt, nullptr);
+    if (rc) return rc;
+  } else {
+    for (int r = 0; r < 2; ++r)
+      hipLaunchKernelGGL(k_init_links, dim3(1), dim3(256), 0, s, (int*)(ws + pl.pv0[r]),
+                         (int*)(ws + pl.nx0[r]), (int*)(ws + pl.len[r][0]),
+                         (int*)(ws + pl.claimR[r]), (int*)(ws + pl.claimL[r]), int64_t(1));
+  }
+  return extract(S, ws, pl, s, true, true, d_faces, cap, d_face_off, d_info);
 }
 
 int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,
@@ -592,20 +767,25 @@ int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int3
   if (n < 1 || n > kMaxN || !d_xyz || !d_ev || !d_block_len || !d_order || !d_info || !d_ws ||
       (run != 0 && run != 1))
     return HULL_EINVAL;
-  Plan pl = make_plan(n);
+  const Opts opt = resolve(nullptr);
+  Plan pl = make_plan(n, 1, opt.seg);
   if (ws_bytes < pl.total) return HULL_EWORKSPACE;
   char* ws = (char*)d_ws;
   Header* h = (Header*)(ws + pl.header);
   init_header(h, s);
-  int32_t rc = sort_points(d_xyz, n, ws, pl, s);
+  int64_t* off = (int64_t*)(ws + pl.off1);
+  hipLaunchKernelGGL(k_set_off1, dim3(1), dim3(64), 0, s, off, n);
+  Sched S{};
+  S.off = off;
+  S.H = 1;
+  int32_t rc = sort_points(d_xyz, n, nullptr, 1, ws, pl, s);
   if (rc) return rc;
   int L = levels_for(n);
   if (level >= 0 && level < L) L = level;
-  int buf = 0;
-  rc = run_levels(n, ws, pl, s, run == 0, run == 1, L, &buf, nullptr);
+  rc = run_levels(n, S, ws, pl, s, run == 0, run == 1, L, opt, nullptr);
   if (rc) return rc;
   hipLaunchKernelGGL(k_export_movies, dim3(grid_for(2 * n, 1024)), dim3(256), 0, s,
-                     (const Event*)(ws + pl.ev[run][buf]), (const int*)(ws + pl.len[run][buf]),
+                     (const Event*)(ws + pl.ev[run][L & 1]), (const int*)(ws + pl.len[run][L & 1]),
                      (const int4*)(ws + pl.pts), n, int64_t(1) << L, d_ev, d_block_len, d_order,
                      h);
   hipLaunchKernelGGL(k_info_small, dim3(1), dim3(64), 0, s, d_info, h);
@@ -632,7 +812,13 @@ const char* hull_strerror(int32_t code) {
 int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes) {
   (void)flags;
   if (!bytes || n < 0 || n > hull::kMaxN) return HULL_EINVAL;
-  *bytes = hull::make_plan(n).total;
+  *bytes = hull::make_plan(n, 1, 8).total;
+  return HULL_OK;
+}
+
+int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* bytes) {
+  if (!bytes || total_points < 0 || total_points > hull::kMaxTotal || H < 1) return HULL_EINVAL;
+  *bytes = hull::make_plan(total_points, H, 8).total;
   return HULL_OK;
 }
 
@@ -654,6 +840,14 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
   if (!events) return HULL_EINVAL;
   return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
                          true, events, nevents);
+}
+
+int32_t hull_full_batched(const int32_t* d_xyz, const int64_t* d_offsets, const int64_t* h_offsets,
+                          int64_t H, int32_t* d_faces, int64_t cap, int64_t* d_face_offsets,
+                          int64_t* d_info, void* d_ws, size_t ws_bytes,
+                          const hull_schedule_t* schedule, void* stream) {
+  return hull::batched(d_xyz, d_offsets, h_offsets, H, d_faces, cap, d_face_offsets, d_info, d_ws,
+                       ws_bytes, schedule, (hipStream_t)stream);
 }
 
 int32_t hull_movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,

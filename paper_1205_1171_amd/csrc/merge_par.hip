@@ -27,10 +27,6 @@
 
 namespace hull {
 
-__device__ __forceinline__ int64_t in_block_start(int64_t q, int k) {
-  return ((q >> 1) >> (k - 1)) << (k - 1);
-}
-
 // # of events among slots [base, base + len) strictly before X.
 __device__ int count_before(const int4* pts, const Event* ev, const double* tau, int64_t base,
                             int len, const Cand& X, int zs) {
@@ -42,66 +38,6 @@ __device__ int count_before(const int4* pts, const Event* ev, const double* tau,
     else hi = mid;
   }
   return lo;
-}
-
-__global__ void __launch_bounds__(256) k_par_zero(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts) return;
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    R.cntR[p] = 0;
-    R.cntL[p] = 0;
-    R.curR[p] = 0;
-    R.curL[p] = 0;
-  }
-}
-
-// Which links an event changes: nx(a) and pv(b); an insertion also sets
-// nx(w) and pv(w).
-__global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts || P.h->err) return;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * P.n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    int64_t sb = in_block_start(q, P.k);
-    if (q - 2 * sb >= R.len_in[sb]) continue;
-    Event E = R.ev_in[q];
-    atomicAdd(&R.cntR[E.a], 1);
-    atomicAdd(&R.cntL[E.b], 1);
-    if (E.kind) {
-      atomicAdd(&R.cntR[E.w], 1);
-      atomicAdd(&R.cntL[E.w], 1);
-    }
-  }
-}
-
-// Lists of link changes: every entry is the child event itself (its kind
-// field also carries its slot, kind | slot << 1, the sort key) and its time.
-__global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts || P.h->err) return;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < 2 * P.n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    int64_t sb = in_block_start(q, P.k);
-    if (q - 2 * sb >= R.len_in[sb]) continue;
-    Event E = R.ev_in[q];
-    double t = R.tau_in[q];
-    Event X{E.a, E.w, E.b, (int)(q << 1) | E.kind};
-    int j = R.offR[E.a] + atomicAdd(&R.curR[E.a], 1);
-    R.entR[j] = X;
-    R.entRt[j] = t;
-    j = R.offL[E.b] + atomicAdd(&R.curL[E.b], 1);
-    R.entL[j] = X;
-    R.entLt[j] = t;
-    if (E.kind) {
-      j = R.offR[E.w] + atomicAdd(&R.curR[E.w], 1);
-      R.entR[j] = X;
-      R.entRt[j] = t;
-      j = R.offL[E.w] + atomicAdd(&R.curL[E.w], 1);
-      R.entL[j] = X;
-      R.entLt[j] = t;
-    }
-  }
 }
 
 // Sort one point's entries by slot (= time order within the child movie).
@@ -121,16 +57,6 @@ __device__ void sort_entries(Event* a, double* t, int k) {
       a[j] = x;
       t[j] = y;
     }
-}
-
-__global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts || P.h->err) return;
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P.n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    sort_entries(R.entR + R.offR[p], R.entRt + R.offR[p], R.cntR[p]);
-    sort_entries(R.entL + R.offL[p], R.entLt + R.offL[p], R.cntL[p]);
-  }
 }
 
 // Link of p after an event that changes it.
@@ -173,10 +99,13 @@ struct Endpoint {
 
 __device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) {
   int p = X.p;
-  X.oR = R.offR[p];
-  X.nR = R.cntR[p];
-  X.oL = R.offL[p];
-  X.nL = R.cntL[p];
+  // a point no child event touched at this level has empty lists (its
+  // counters still hold an earlier level's values)
+  const bool hasR = R.claimR[p] == R.stamp, hasL = R.claimL[p] == R.stamp;
+  X.oR = hasR ? R.offR[p] : 0;
+  X.nR = hasR ? R.cntR[p] : 0;
+  X.oL = hasL ? R.offL[p] : 0;
+  X.nL = hasL ? R.cntL[p] : 0;
   X.cr = first_after(R, R.entR, R.entRt, X.oR, X.nR, haveT, T);
   X.cl = first_after(R, R.entL, R.entLt, X.oL, X.nL, haveT, T);
   X.nx = X.cr > 0 ? right_after(R.entR[X.oR + X.cr - 1], p) : R.nx0[p];
@@ -346,30 +275,162 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
   return nb;
 }
 
-// Segments per merge, from the child movie lengths.
-__global__ void __launch_bounds__(256) k_par_segcount(ParLevel P) {
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); \
+       i += (int64_t)gridDim.x * blockDim.x)
+
+// Per merge: child event count and walk segments; counters reset.
+__global__ void __launch_bounds__(256) k_par_prep(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int64_t width = int64_t(1) << P.k;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g <= P.merges;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    if (g == P.merges || P.h->err) {
-      R.segS[g] = g == P.merges ? 0 : 1;
-      continue;
+  const int merges = P.S.moff[P.S.H];
+  const int64_t half = int64_t(1) << (P.k - 1);
+  GRID_STRIDE(g, (int64_t)merges + 1) {
+    if (g == 0) {
+      R.ctr[0] = R.ctr[1] = R.ctr[2] = 0;
+      R.ctr[4] = merges;
     }
-    int64_t s = g * width, m = s + (width >> 1);
-    R.segS[g] = segments_for(R.len_in[s], R.len_in[m], P.seg_events);
+    if (g < merges && !P.h->err) {
+      const int2 se = P.S.mlist[g];
+      const int nL = R.len_in[se.x], nR = R.len_in[se.x + half];
+      R.ecnt[g] = nL + nR;
+      R.segS[g] = segments_for(nL, nR, P.seg_events);
+    } else {
+      R.ecnt[g] = 0;
+      R.segS[g] = 0;
+    }
+    R.nB[g] = 0;
+  }
+}
+
+// Level totals after the scans: child events and walk segments.
+__global__ void k_par_totals(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts || threadIdx.x) return;
+  const int merges = R.ctr[4];
+  R.ctr[5] = R.eoff[merges];
+  R.ctr[6] = R.segBase[merges];
+}
+
+__global__ void k_par_btotal(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts || threadIdx.x) return;
+  R.ctr[7] = R.boff[R.ctr[4]];
+}
+
+// The compact list of child events (slot and merge of each), and the
+// link-change counters of their points cleared.
+__global__ void __launch_bounds__(256) k_par_enum(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  const int merges = R.ctr[4], E = R.ctr[5];
+  const int64_t half = int64_t(1) << (P.k - 1);
+  GRID_STRIDE(c, E) {
+    const int g = find_owner(R.eoff, merges, c);
+    const int2 se = P.S.mlist[g];
+    const int64_t s = se.x, m = s + half;
+    const int nL = R.len_in[s];
+    const int64_t i = c - R.eoff[g];
+    const int64_t slot = i < nL ? 2 * s + i : 2 * m + (i - nL);
+    R.cslot[c] = (int)slot;
+    R.cmerge[c] = g;
+    const Event X = R.ev_in[slot];
+    R.cntR[X.a] = 0;
+    R.curR[X.a] = 0;
+    R.cntL[X.b] = 0;
+    R.curL[X.b] = 0;
+    if (X.kind) {
+      R.cntR[X.w] = 0;
+      R.curR[X.w] = 0;
+      R.cntL[X.w] = 0;
+      R.curL[X.w] = 0;
+    }
+  }
+}
+
+// Which links an event changes: nx(a) and pv(b); an insertion also sets
+// nx(w) and pv(w).
+__global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  GRID_STRIDE(c, R.ctr[5]) {
+    const Event X = R.ev_in[R.cslot[c]];
+    atomicAdd(&R.cntR[X.a], 1);
+    atomicAdd(&R.cntL[X.b], 1);
+    if (X.kind) {
+      atomicAdd(&R.cntR[X.w], 1);
+      atomicAdd(&R.cntL[X.w], 1);
+    }
+  }
+}
+
+// One list per touched (point, side), allocated by whichever event claims it
+// first at this level.
+__device__ __forceinline__ void claim(const ParRun& R, int p, int side, int stamp) {
+  int* cl = side ? R.claimL : R.claimR;
+  if (atomicExch(&cl[p], stamp) == stamp) return;
+  int* off = side ? R.offL : R.offR;
+  const int* cnt = side ? R.cntL : R.cntR;
+  off[p] = atomicAdd(&R.ctr[side], cnt[p]);
+  R.touched[atomicAdd(&R.ctr[2], 1)] = (p << 1) | side;
+}
+
+__global__ void __launch_bounds__(256) k_par_alloc(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  GRID_STRIDE(c, R.ctr[5]) {
+    const Event X = R.ev_in[R.cslot[c]];
+    claim(R, X.a, 0, R.stamp);
+    claim(R, X.b, 1, R.stamp);
+    if (X.kind) {
+      claim(R, X.w, 0, R.stamp);
+      claim(R, X.w, 1, R.stamp);
+    }
+  }
+}
+
+// Lists of link changes: every entry is the child event itself (its kind
+// field also carries its slot, kind | slot << 1, the sort key) and its time.
+__global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  GRID_STRIDE(c, R.ctr[5]) {
+    const int q = R.cslot[c];
+    const Event E = R.ev_in[q];
+    const double t = R.tau_in[q];
+    const Event X{E.a, E.w, E.b, (q << 1) | E.kind};
+    int j = R.offR[E.a] + atomicAdd(&R.curR[E.a], 1);
+    R.entR[j] = X;
+    R.entRt[j] = t;
+    j = R.offL[E.b] + atomicAdd(&R.curL[E.b], 1);
+    R.entL[j] = X;
+    R.entLt[j] = t;
+    if (E.kind) {
+      j = R.offR[E.w] + atomicAdd(&R.curR[E.w], 1);
+      R.entR[j] = X;
+      R.entRt[j] = t;
+      j = R.offL[E.w] + atomicAdd(&R.curL[E.w], 1);
+      R.entL[j] = X;
+      R.entLt[j] = t;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  GRID_STRIDE(t, R.ctr[2]) {
+    const int x = R.touched[t], p = x >> 1;
+    if (x & 1) sort_entries(R.entL + R.offL[p], R.entLt + R.offL[p], R.cntL[p]);
+    else sort_entries(R.entR + R.offR[p], R.entRt + R.offR[p], R.cntR[p]);
   }
 }
 
 __global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < P.merges;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int b = R.segBase[g], S = R.segS[g];
-    for (int i = 0; i < S; ++i) R.segMerge[b + i] = (int)g;
-  }
+  const int merges = R.ctr[4];
+  GRID_STRIDE(t, R.ctr[6]) R.segMerge[t] = find_owner(R.segBase, merges, t);
 }
 
 // Pass 1 counts each segment's bridge events; pass 2 writes them at their
@@ -377,170 +438,172 @@ __global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
 __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t > P.seg_cap) return;
-  const int total = R.segBase[P.merges];
-  if (t >= total) {
-    if (!write) R.segCnt[t] = 0;
-    return;
-  }
-  const int g = R.segMerge[t];
-  const int first = R.segBase[g], S = R.segS[g], i = (int)(t - first);
-  const int64_t width = int64_t(1) << P.k;
-  const int64_t s = g * width, m = s + (width >> 1), e = std::min(s + width, P.n);
-  if (P.h->err) {
-    if (!write) R.segCnt[t] = 0;
-    else if (i == 0) {
-      R.nB[s] = 0;
-      R.uv0[s] = make_int2(0, 0);
+  const int total = R.ctr[6];
+  const int64_t half = int64_t(1) << (P.k - 1);
+  GRID_STRIDE(t, (int64_t)total + 1) {
+    if (t == total) {  // the scan reads one entry past the last segment
+      if (!write) R.segCnt[t] = 0;
+      continue;
     }
-    return;
+    const int g = R.segMerge[t];
+    const int first = R.segBase[g], S = R.segS[g], i = (int)(t - first);
+    const int2 se = P.S.mlist[g];
+    const int64_t s = se.x, m = s + half, e = se.y;
+    if (P.h->err) {
+      if (!write) R.segCnt[t] = 0;
+      else if (i == 0) {
+        R.nB[g] = 0;
+        R.uv0[g] = make_int2(0, 0);
+      }
+      continue;
+    }
+    if (!write) {
+      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, nullptr, 0, nullptr);
+      continue;
+    }
+    const int64_t off = R.segOff[t] - R.segOff[first];
+    const int cap = (int)(2 * (e - s) - off);
+    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.btau + 2 * s + off,
+                 R.buv + 2 * s + off, cap, i == 0 ? &R.uv0[g] : nullptr);
+    if (i == 0) R.nB[g] = R.segOff[first + S] - R.segOff[first];
   }
-  if (!write) {
-    R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, nullptr, 0, nullptr);
-    return;
-  }
-  int64_t off = R.segOff[t] - R.segOff[first];
-  int cap = (int)(2 * (e - s) - off);
-  walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.btau + 2 * s + off,
-               R.buv + 2 * s + off, cap, i == 0 ? &R.uv0[s] : nullptr);
-  if (i == 0) R.nB[s] = R.segOff[first + S] - R.segOff[first];
 }
 
 // Survival of every child event, and the number of bridge events before it.
 __global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int k = P.k;
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q <= 2 * P.n;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    if (q == 2 * P.n || P.h->err) {
-      R.surv[q] = 0;
+  const int E = R.ctr[5];
+  const int64_t half = int64_t(1) << (P.k - 1);
+  const bool err = P.h->err != 0;
+  GRID_STRIDE(c, (int64_t)E + 1) {
+    if (c == E || err) {
+      R.surv[c] = 0;
       continue;
     }
-    int64_t sb = in_block_start(q, k);
-    int64_t g = sb >> k;
-    if (g >= P.merges || q - 2 * sb >= R.len_in[sb]) {
-      R.surv[q] = 0;
-      continue;
-    }
-    int64_t s = g << k;
-    bool isL = sb == s;
-    Cand c = cand_of(R.ev_in, R.tau_in, q);
-    int nb = R.nB[s];
-    int j = count_before(R.pts, R.bev, R.btau, 2 * s, nb, c, R.zs);
-    int2 ref = j > 0 ? R.buv[2 * s + j - 1] : R.uv0[s];
-    R.surv[q] = isL ? (c.t.w < ref.x) : (c.t.w > ref.y);
-    R.jb[q] = j;
+    const int g = R.cmerge[c];
+    const int q = R.cslot[c];
+    const int64_t s = P.S.mlist[g].x, m = s + half;
+    const bool isL = q < 2 * m;
+    const Cand x = cand_of(R.ev_in, R.tau_in, q);
+    const int j = count_before(R.pts, R.bev, R.btau, 2 * s, R.nB[g], x, R.zs);
+    const int2 ref = j > 0 ? R.buv[2 * s + j - 1] : R.uv0[g];
+    R.surv[c] = isL ? (x.t.w < ref.x) : (x.t.w > ref.y);
+    R.jb[c] = j;
   }
 }
 
-// Scatter: child survivors (indices [0, 2n)) and bridge events ([2n, 4n))
-// to their places in the merged movies.
+// Scatter: child survivors, then bridge events, to their places in the
+// merged movies; then every merge writes its length and splices its -inf
+// chains (no kernel of this level reads the -inf links after the walk).
 __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
   const bool err = P.h->err != 0;
-  const int k = P.k;
-  const int64_t n = P.n, width = int64_t(1) << k, half = width >> 1;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 4 * n;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    if (t < 2 * n) {
-      int64_t q = t;
-      if (err || !R.surv[q]) continue;
-      int64_t sb = in_block_start(q, k);
-      int64_t s = (sb >> k) << k, m = s + half;
-      bool isL = sb == s;
-      Cand c = cand_of(R.ev_in, R.tau_in, q);
+  const int merges = R.ctr[4], E = R.ctr[5], Bt = R.ctr[7];
+  const int64_t half = int64_t(1) << (P.k - 1);
+  GRID_STRIDE(t, (int64_t)E + Bt + merges) {
+    if (t < E) {
+      const int64_t c = t;
+      if (err || !R.surv[c]) continue;
+      const int g = R.cmerge[c];
+      const int q = R.cslot[c];
+      const int2 se = P.S.mlist[g];
+      const int64_t s = se.x, m = s + half, e = se.y;
+      const int nL = R.len_in[s], nR = R.len_in[m];
+      const int c0 = R.eoff[g], cR = c0 + nL;
+      const Cand x = cand_of(R.ev_in, R.tau_in, q);
       int64_t pos;
-      if (isL) {
-        int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, R.len_in[m], c, R.zs);
-        pos = (R.pre[q] - R.pre[2 * s]) + (R.pre[2 * m + idx] - R.pre[2 * m]) + R.jb[q];
+      if (q < 2 * m) {
+        const int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, nR, x, R.zs);
+        pos = (R.pre[c] - R.pre[c0]) + (R.pre[cR + idx] - R.pre[cR]) + R.jb[c];
       } else {
-        int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, R.len_in[s], c, R.zs);
-        pos = (R.pre[2 * s + idx] - R.pre[2 * s]) + (R.pre[q] - R.pre[2 * m]) + R.jb[q];
+        const int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, nL, x, R.zs);
+        pos = (R.pre[c0 + idx] - R.pre[c0]) + (R.pre[c] - R.pre[cR]) + R.jb[c];
       }
-      if (pos >= 2 * (std::min(s + width, n) - s)) {
-        atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
-        continue;
-      }
-      R.ev_out[2 * s + pos] = R.ev_in[q];
-      R.tau_out[2 * s + pos] = c.st;
-    } else {
-      int64_t q = t - 2 * n;
-      int64_t g = (q >> 1) >> k;
-      if (g >= P.merges) continue;
-      int64_t s = g << k, m = s + half, e = std::min(s + width, n);
-      int64_t j = q - 2 * s;
-      int nb = R.nB[s];
-      if (j == 0) {
-        // every merge writes its length, also after an error (then 0)
-        int cnt = err ? 0 : (R.pre[2 * e] - R.pre[2 * s]) + nb;
-        R.len_out[s] = cnt <= 2 * (e - s) ? cnt : 0;
-        if (cnt > 2 * (e - s)) atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
-        // splice the -inf chains at the -inf bridge (no kernel of this level
-        // reads the -inf links after the walk)
-        if (!err) {
-          int2 b0 = R.uv0[s];
-          R.nx0[b0.x] = b0.y;
-          R.pv0[b0.y] = b0.x;
-        }
-      }
-      if (err || j >= nb) continue;
-      Cand c = cand_of(R.bev, R.btau, q);
-      int iL = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, R.len_in[s], c, R.zs);
-      int iR = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, R.len_in[m], c, R.zs);
-      int64_t pos = j + (R.pre[2 * s + iL] - R.pre[2 * s]) + (R.pre[2 * m + iR] - R.pre[2 * m]);
       if (pos >= 2 * (e - s)) {
         atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
         continue;
       }
-      R.ev_out[2 * s + pos] = R.bev[q];
-      R.tau_out[2 * s + pos] = c.st;
+      R.ev_out[2 * s + pos] = R.ev_in[q];
+      R.tau_out[2 * s + pos] = x.st;
+    } else if (t < (int64_t)E + Bt) {
+      if (err) continue;
+      const int64_t b = t - E;
+      const int g = find_owner(R.boff, merges, b);
+      const int j = (int)(b - R.boff[g]);
+      const int2 se = P.S.mlist[g];
+      const int64_t s = se.x, m = s + half, e = se.y;
+      const int nL = R.len_in[s], nR = R.len_in[m];
+      const int c0 = R.eoff[g], cR = c0 + nL;
+      const Cand x = cand_of(R.bev, R.btau, 2 * s + j);
+      const int iL = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, nL, x, R.zs);
+      const int iR = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, nR, x, R.zs);
+      const int64_t pos = j + (R.pre[c0 + iL] - R.pre[c0]) + (R.pre[cR + iR] - R.pre[cR]);
+      if (pos >= 2 * (e - s)) {
+        atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+        continue;
+      }
+      R.ev_out[2 * s + pos] = R.bev[2 * s + j];
+      R.tau_out[2 * s + pos] = x.st;
+    } else {
+      const int g = (int)(t - E - Bt);
+      const int2 se = P.S.mlist[g];
+      const int64_t s = se.x, e = se.y;
+      // every merge writes its length, also after an error (then 0)
+      const int cnt = err ? 0 : (R.pre[R.eoff[g + 1]] - R.pre[R.eoff[g]]) + R.nB[g];
+      R.len_out[s] = cnt <= 2 * (e - s) ? cnt : 0;
+      if (cnt > 2 * (e - s)) atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+      if (!err) {
+        const int2 b0 = R.uv0[g];
+        R.nx0[b0.x] = b0.y;
+        R.pv0[b0.y] = b0.x;
+      }
     }
   }
 }
 
-static unsigned blocks_for(int64_t work, int64_t cap = 8192) {
-  int64_t b = (work + 255) / 256;
-  if (b < 1) b = 1;
-  if (b > cap) b = cap;
-  return (unsigned)b;
-}
-
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
-  const int64_t n = P.n;
-  hipLaunchKernelGGL(k_par_zero, dim3(blocks_for(n), 2), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_par_count, dim3(blocks_for(2 * n), 2), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_par_segcount, dim3(blocks_for(P.merges + 1), 2), dim3(256), 0, s, P);
+  const dim3 g2(kStrideBlocks, 2), b256(256);
+  hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
   for (int r = 0; r < 2; ++r) {
     const ParRun& R = P.run[r];
     if (!R.pts) continue;
-    int32_t rc = exclusive_scan_i32(R.cntR, R.offR, n, partials, s);
-    if (!rc) rc = exclusive_scan_i32(R.cntL, R.offL, n, partials, s);
-    if (!rc) rc = exclusive_scan_i32(R.segS, R.segBase, P.merges + 1, partials, s);
+    int32_t rc = exclusive_scan_dev(R.ecnt, R.eoff, R.ctr + 4, 1, P.S.mcap + 1, partials, s);
+    if (!rc) rc = exclusive_scan_dev(R.segS, R.segBase, R.ctr + 4, 1, P.S.mcap + 1, partials, s);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_par_fill, dim3(blocks_for(2 * n), 2), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_par_sort, dim3(blocks_for(n), 2), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_par_segtable, dim3(blocks_for(P.merges), 2), dim3(256), 0, s, P);
-  const unsigned wg = (unsigned)((P.seg_cap + 1 + 63) / 64);
-  hipLaunchKernelGGL(k_par_walk, dim3(wg, 2), dim3(64), 0, s, P, 0);
+  hipLaunchKernelGGL(k_par_totals, dim3(1, 2), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(k_par_enum, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_count, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_alloc, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_fill, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_sort, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_segtable, g2, b256, 0, s, P);
+  const dim3 gw(16384, 2), b64(64);
+  hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 0);
   for (int r = 0; r < 2; ++r) {
     const ParRun& R = P.run[r];
     if (!R.pts) continue;
-    int32_t rc = exclusive_scan_i32(R.segCnt, R.segOff, P.seg_cap + 1, partials, s);
+    int32_t rc = exclusive_scan_dev(R.segCnt, R.segOff, R.ctr + 6, 1, P.seg_cap + 1, partials, s);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_par_walk, dim3(wg, 2), dim3(64), 0, s, P, 1);
-  hipLaunchKernelGGL(k_par_classify, dim3(blocks_for(2 * n + 1), 2), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 1);
   for (int r = 0; r < 2; ++r) {
     const ParRun& R = P.run[r];
     if (!R.pts) continue;
-    int32_t rc = exclusive_scan_i32(R.surv, R.pre, 2 * n + 1, partials, s);
+    int32_t rc = exclusive_scan_dev(R.nB, R.boff, R.ctr + 4, 1, P.S.mcap + 1, partials, s);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(k_par_scatter, dim3(blocks_for(4 * n), 2), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(k_par_btotal, dim3(1, 2), dim3(64), 0, s, P);
+  hipLaunchKernelGGL(k_par_classify, g2, b256, 0, s, P);
+  for (int r = 0; r < 2; ++r) {
+    const ParRun& R = P.run[r];
+    if (!R.pts) continue;
+    int32_t rc = exclusive_scan_dev(R.surv, R.pre, R.ctr + 5, 1, P.ecap + 1, partials, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_par_scatter, g2, b256, 0, s, P);
   HULL_LAUNCH_CHECK();
   return HULL_OK;
 }

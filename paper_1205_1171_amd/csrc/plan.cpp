@@ -1,4 +1,4 @@
-// Workspace plan: offsets of every device buffer of a single hull (host).
+// Workspace plan: offsets of every device buffer for n points in H hulls (host).
 #include <algorithm>
 
 #include "common.hpp"
@@ -7,16 +7,22 @@ namespace hull {
 
 static int64_t scan_partials_needed(int64_t len) { return (len + kScanBlock - 1) / kScanBlock; }
 
-// ---------------------------------------------------------------------------
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Plan make_plan(int64_t n) {
+Plan make_plan(int64_t n, int64_t H, int min_seg) {
   Plan p{};
-  int64_t nn = n > 0 ? n : 1;
+  const int64_t nn = n > 0 ? n : 1;
+  const int64_t hh = H > 0 ? H : 1;
   p.n = n;
+  p.H = H;
   p.tiles = (nn + kTile - 1) / kTile;
   p.count_len = p.tiles * kBuckets;
-  p.partial_len = std::max(scan_partials_needed(p.count_len), scan_partials_needed(2 * nn + 1)) + 1;
+  // merges of one level: sum over hulls of floor(ceil(n_h / w) / 2) <= n / 2
+  p.mcap = nn / 2 + 1;
+  // walk segments of one level: sum over merges of 1 + events / G, events <= 2n
+  p.seg_cap = p.mcap + (2 * nn) / std::max(min_seg, 1) + 1;
+  int64_t longest = std::max<int64_t>({p.count_len, 2 * nn + 1, p.seg_cap + 1, hh + 1});
+  p.partial_len = scan_partials_needed(longest) + 2;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -31,6 +37,15 @@ Plan make_plan(int64_t n) {
   p.counts = take(p.count_len * 4);
   p.partials = take(p.partial_len * 4);
   p.pts = take(nn * sizeof(int4));
+  p.hid = take(nn * 4);
+  p.off1 = take(2 * sizeof(int64_t));
+  p.mcnt = take((hh + 1) * 4);
+  p.moff = take((hh + 1) * 4);
+  p.tcnt = take((hh + 1) * 4);
+  p.toff = take((hh + 1) * 4);
+  p.tlist = take(hh * 4);
+  p.mlist = take(p.mcap * sizeof(int2));
+  p.fcnt = take((hh + 1) * 4);
   for (int r = 0; r < 2; ++r) {
     p.pv0[r] = take(nn * 4);
     p.nx0[r] = take(nn * 4);
@@ -47,20 +62,29 @@ Plan make_plan(int64_t n) {
     p.offL[r] = take(nn * 4);
     p.curR[r] = take(nn * 4);
     p.curL[r] = take(nn * 4);
+    p.claimR[r] = take(nn * 4);
+    p.claimL[r] = take(nn * 4);
     p.entR[r] = take(4 * nn * sizeof(Event));
     p.entL[r] = take(4 * nn * sizeof(Event));
     p.entRt[r] = take(4 * nn * sizeof(double));
     p.entLt[r] = take(4 * nn * sizeof(double));
-    p.segS[r] = take((nn + 2) * 4);
-    p.segBase[r] = take((nn + 2) * 4);
-    p.segMerge[r] = take((nn + 2) * 4);
-    p.segCnt[r] = take((nn + 2) * 4);
-    p.segOff[r] = take((nn + 2) * 4);
+    p.ctr[r] = take(4 * sizeof(int32_t));
+    p.touched[r] = take(2 * nn * 4);
+    p.ecnt[r] = take((p.mcap + 1) * 4);
+    p.eoff[r] = take((p.mcap + 1) * 4);
+    p.cslot[r] = take(2 * nn * 4);
+    p.cmerge[r] = take(2 * nn * 4);
+    p.segS[r] = take((p.mcap + 1) * 4);
+    p.segBase[r] = take((p.mcap + 1) * 4);
+    p.segMerge[r] = take((p.seg_cap + 1) * 4);
+    p.segCnt[r] = take((p.seg_cap + 1) * 4);
+    p.segOff[r] = take((p.seg_cap + 1) * 4);
     p.bev[r] = take(2 * nn * sizeof(Event));
     p.btau[r] = take(2 * nn * sizeof(double));
     p.buv[r] = take(2 * nn * sizeof(int2));
-    p.nB[r] = take(nn * 4);
-    p.uv0[r] = take(nn * sizeof(int2));
+    p.nB[r] = take((p.mcap + 1) * 4);
+    p.boff[r] = take((p.mcap + 1) * 4);
+    p.uv0[r] = take(p.mcap * sizeof(int2));
     p.surv[r] = take((2 * nn + 1) * 4);
     p.jb[r] = take(2 * nn * 4);
     p.pre[r] = take((2 * nn + 1) * 4);

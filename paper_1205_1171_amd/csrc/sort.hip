@@ -63,29 +63,57 @@ __global__ void k_nbits(Header* h) {
 }
 
 // ---------------------------------------------------------------------------
-// Radix passes.  Pass 0 reads keys straight from xyz (value = input index);
-// later passes ping-pong between (keys0, vals0) and (keys1, vals1).  A pass
-// whose digit lies above the key's bit length is skipped.
+// Radix passes.  The x passes sort the key x - min(x) (value = input index);
+// passes whose digit lies above the key's bit length are skipped.  For a
+// batch, stable passes on the hull id follow, so the final order is (hull,
+// x, input index).  Executed pass e reads buffer (e - 1) & 1 (pass 0 reads
+// xyz) and writes buffer e & 1; the buffers are chosen on the device.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t load_key(const int32_t* xyz, const uint32_t* keys, int64_t p,
-                                             int pass, int minx) {
-  return pass == 0 ? (uint32_t)((int64_t)xyz[3 * p] - minx) : keys[p];
+struct RadixBufs {
+  uint32_t* keys[2];
+  int32_t* vals[2];
+};
+
+__device__ __forceinline__ int x_passes(const Header* h) {
+  int p = (h->nbits + kRadixBits - 1) / kRadixBits;
+  return p < 1 ? 1 : p;
+}
+
+// Digit of element p for (kind, d): kind 0 = x digit d, kind 1 = hull digit d.
+__device__ __forceinline__ uint32_t radix_key(const int32_t* xyz, const RadixBufs& B,
+                                              const int32_t* hid, int64_t p, int e, int kind,
+                                              int minx, int32_t* val) {
+  if (kind == 0) {
+    if (e == 0) {
+      *val = (int32_t)p;
+      return (uint32_t)((int64_t)xyz[3 * p] - minx);
+    }
+    *val = B.vals[(e - 1) & 1][p];
+    return B.keys[(e - 1) & 1][p];
+  }
+  int v = B.vals[(e - 1) & 1][p];
+  *val = v;
+  return (uint32_t)hid[v];
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-    k_radix_hist(const int32_t* __restrict__ xyz, const uint32_t* __restrict__ keys, int64_t n,
-                 int pass, int tiles, int32_t* __restrict__ counts, const Header* h) {
-  if (pass > 0 && pass * kRadixBits >= h->nbits) return;
+    k_radix_hist(const int32_t* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
+                 int64_t n, int kind, int d, int tiles, int32_t* __restrict__ counts,
+                 const Header* h) {
+  const int xp = x_passes(h);
+  if (kind == 0 && d >= xp) return;
+  const int e = kind == 0 ? d : xp + d;
   __shared__ int hist[kBuckets];
   hist[threadIdx.x] = 0;
   __syncthreads();
-  int minx = h->minx;
-  int64_t base = (int64_t)blockIdx.x * kTile;
+  const int minx = h->minx;
+  const int64_t base = (int64_t)blockIdx.x * kTile;
   for (int j = 0; j < kSortItems; ++j) {
     int64_t p = base + j * kSortThreads + threadIdx.x;
     if (p < n) {
-      uint32_t k = load_key(xyz, keys, p, pass, minx);
-      atomicAdd(&hist[(k >> (pass * kRadixBits)) & (kBuckets - 1)], 1);
+      int32_t v;
+      uint32_t k = radix_key(xyz, B, hid, p, e, kind, minx, &v);
+      atomicAdd(&hist[(k >> (d * kRadixBits)) & (kBuckets - 1)], 1);
     }
   }
   __syncthreads();
@@ -93,11 +121,12 @@ __global__ void __launch_bounds__(kSortThreads)
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-    k_radix_scatter(const int32_t* __restrict__ xyz, const uint32_t* __restrict__ keys,
-                    const int32_t* __restrict__ vals, int64_t n, int pass, int tiles,
-                    const int32_t* __restrict__ offsets, uint32_t* __restrict__ keys_out,
-                    int32_t* __restrict__ vals_out, const Header* h) {
-  if (pass > 0 && pass * kRadixBits >= h->nbits) return;
+    k_radix_scatter(const int32_t* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
+                    int64_t n, int kind, int d, int tiles, const int32_t* __restrict__ offsets,
+                    const Header* h) {
+  const int xp = x_passes(h);
+  if (kind == 0 && d >= xp) return;
+  const int e = kind == 0 ? d : xp + d;
   constexpr int kWaves = kSortThreads / 64;
   __shared__ int base[kBuckets];
   __shared__ int wcnt[kWaves][kBuckets];
@@ -106,57 +135,71 @@ __global__ void __launch_bounds__(kSortThreads)
   const int minx = h->minx;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t tbase = (int64_t)blockIdx.x * kTile;
+  uint32_t* kout = B.keys[e & 1];
+  int32_t* vout = B.vals[e & 1];
   for (int j = 0; j < kSortItems; ++j) {
     for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
     __syncthreads();
     int64_t p = tbase + j * kSortThreads + tid;
     bool valid = p < n;
     uint32_t k = 0;
-    int v = 0;
-    if (valid) {
-      k = load_key(xyz, keys, p, pass, minx);
-      v = pass == 0 ? (int)p : vals[p];
-    }
-    int d = (k >> (pass * kRadixBits)) & (kBuckets - 1);
+    int32_t v = 0;
+    if (valid) k = radix_key(xyz, B, hid, p, e, kind, minx, &v);
+    int dg = (k >> (d * kRadixBits)) & (kBuckets - 1);
     // lanes of this wave holding the same digit
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < kRadixBits; ++b) {
-      uint64_t on = __ballot((d >> b) & 1);
-      peers &= ((d >> b) & 1) ? on : ~on;
+      uint64_t on = __ballot((dg >> b) & 1);
+      peers &= ((dg >> b) & 1) ? on : ~on;
     }
     int rank = __popcll(peers & lt_mask);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    if (valid && rank == 0) wcnt[wave][dg] = __popcll(peers);
     __syncthreads();
     int pos = 0;
     if (valid) {
-      pos = base[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      pos = base[dg] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
     }
     __syncthreads();
     int add = 0;
     for (int w = 0; w < kWaves; ++w) add += wcnt[w][tid];
     base[tid] += add;
     if (valid) {
-      keys_out[pos] = k;
-      vals_out[pos] = v;
+      if (kind == 0) kout[pos] = k;
+      vout[pos] = v;
     }
     __syncthreads();
   }
 }
 
-// Gather the points in rank order; the sorted values sit in the buffer the
-// last executed pass wrote.
+// Hull id of every input point (batches).
+__global__ void __launch_bounds__(256) k_hull_ids(const int64_t* __restrict__ off, int64_t H,
+                                                  int64_t n, int32_t* __restrict__ hid) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = H;  // largest h with off[h] <= i
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (off[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    hid[i] = (int32_t)lo;
+  }
+}
+
+// Gather the points in rank order from the buffer of the last executed pass;
+// the fourth component is the index within the point's hull.
 __global__ void __launch_bounds__(256)
-    k_gather(const int32_t* __restrict__ xyz, const int32_t* __restrict__ vals0,
-             const int32_t* __restrict__ vals1, int64_t n, int4* __restrict__ pts,
+    k_gather(const int32_t* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
+             const int64_t* __restrict__ off, int hull_passes, int64_t n, int4* __restrict__ pts,
              const Header* h) {
-  int passes = (h->nbits + kRadixBits - 1) / kRadixBits;
-  if (passes < 1) passes = 1;
-  const int32_t* v = (passes & 1) ? vals0 : vals1;
+  const int e = x_passes(h) + hull_passes - 1;
+  const int32_t* v = B.vals[e & 1];
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
     int i = v[r];
-    pts[r] = make_int4(xyz[3 * (int64_t)i], xyz[3 * (int64_t)i + 1], xyz[3 * (int64_t)i + 2], i);
+    int local = hid ? (int)(i - off[hid[i]]) : i;
+    pts[r] = make_int4(xyz[3 * (int64_t)i], xyz[3 * (int64_t)i + 1], xyz[3 * (int64_t)i + 2], local);
   }
 }
 
@@ -241,31 +284,118 @@ int32_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t len, int32_t
 }
 
 
+// Scan with a length read from device memory (grids sized for the cap;
+// blocks past the actual length exit at once).
+__device__ __forceinline__ int64_t dev_len(const int32_t* d_len, int add, int64_t cap) {
+  int64_t L = (int64_t)(*d_len) + add;
+  return L < 0 ? 0 : (L > cap ? cap : L);
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+    k_scan_tile_sums_dev(const int32_t* __restrict__ in, const int32_t* d_len, int add,
+                         int64_t cap, int32_t* __restrict__ sums) {
+  const int64_t len = dev_len(d_len, add, cap);
+  if ((int64_t)blockIdx.x * kScanBlock >= len) return;
+  __shared__ int wsum[kSortThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int s = 0;
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + j < len) s += in[base + j];
+  int total;
+  block_exclusive_scan(s, wsum, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+    k_scan_sums_dev(int32_t* sums, const int32_t* d_len, int add, int64_t cap) {
+  const int64_t len = dev_len(d_len, add, cap);
+  const int64_t nsums = (len + kScanBlock - 1) / kScanBlock;
+  __shared__ int wsum[kSortThreads / 64];
+  int carry = 0;
+  for (int64_t b = 0; b < nsums; b += kSortThreads) {
+    int64_t q = b + threadIdx.x;
+    int x = q < nsums ? sums[q] : 0;
+    int total;
+    int ex = block_exclusive_scan(x, wsum, total);
+    if (q < nsums) sums[q] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+    k_scan_tiles_dev(const int32_t* __restrict__ in, const int32_t* d_len, int add, int64_t cap,
+                     const int32_t* __restrict__ sums, int32_t* __restrict__ out) {
+  const int64_t len = dev_len(d_len, add, cap);
+  if ((int64_t)blockIdx.x * kScanBlock >= len) return;
+  __shared__ int wsum[kSortThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = base + j < len ? in[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int run = block_exclusive_scan(s, wsum, total) + sums[blockIdx.x];
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < len) out[base + j] = run;
+    run += v[j];
+  }
+}
+
+int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
+                           int64_t cap, int32_t* partials, hipStream_t s) {
+  if (cap <= 0) return HULL_OK;
+  unsigned blocks = (unsigned)((cap + kScanBlock - 1) / kScanBlock);
+  hipLaunchKernelGGL(k_scan_tile_sums_dev, dim3(blocks), dim3(kSortThreads), 0, s, in, d_len, add,
+                     cap, partials);
+  hipLaunchKernelGGL(k_scan_sums_dev, dim3(1), dim3(kSortThreads), 0, s, partials, d_len, add, cap);
+  hipLaunchKernelGGL(k_scan_tiles_dev, dim3(blocks), dim3(kSortThreads), 0, s, in, d_len, add, cap,
+                     partials, out);
+  HULL_LAUNCH_CHECK();
+  return HULL_OK;
+}
+
 void init_header(Header* h, hipStream_t s) {
   hipLaunchKernelGGL(k_header_init, dim3(1), dim3(64), 0, s, h);
 }
 
-int32_t sort_points(const int32_t* d_xyz, int64_t n, char* ws, const Plan& pl, hipStream_t s) {
+int32_t sort_points(const int32_t* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
+                    const Plan& pl, hipStream_t s) {
   Header* h = (Header*)(ws + pl.header);
-  uint32_t* keys[2] = {(uint32_t*)(ws + pl.keys0), (uint32_t*)(ws + pl.keys1)};
-  int32_t* vals[2] = {(int32_t*)(ws + pl.vals0), (int32_t*)(ws + pl.vals1)};
+  RadixBufs B;
+  B.keys[0] = (uint32_t*)(ws + pl.keys0);
+  B.keys[1] = (uint32_t*)(ws + pl.keys1);
+  B.vals[0] = (int32_t*)(ws + pl.vals0);
+  B.vals[1] = (int32_t*)(ws + pl.vals1);
   int32_t* counts = (int32_t*)(ws + pl.counts);
   int32_t* partials = (int32_t*)(ws + pl.partials);
-  int tiles = (int)pl.tiles;
+  int32_t* hid = nullptr;
+  int hull_passes = 0;
+  if (hull_off && H > 1) {
+    hid = (int32_t*)(ws + pl.hid);
+    int hb = 0;
+    while (hb < 31 && ((H - 1) >> hb) != 0) ++hb;
+    hull_passes = (hb + kRadixBits - 1) / kRadixBits;
+  }
+  const int tiles = (int)pl.tiles;
   unsigned eg = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
   if (eg < 1) eg = 1;
   hipLaunchKernelGGL(k_extent, dim3(eg), dim3(256), 0, s, d_xyz, n, h);
   hipLaunchKernelGGL(k_nbits, dim3(1), dim3(64), 0, s, h);
-  for (int pass = 0; pass < 4; ++pass) {
-    int src = (pass + 1) & 1, dst = pass & 1;  // pass 0 writes buffer 0
-    hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, keys[src], n,
-                       pass, tiles, counts, h);
-    int32_t rc = exclusive_scan_i32(counts, counts, pl.count_len, partials, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, keys[src],
-                       vals[src], n, pass, tiles, counts, keys[dst], vals[dst], h);
+  if (hid) hipLaunchKernelGGL(k_hull_ids, dim3(eg), dim3(256), 0, s, hull_off, H, n, hid);
+  for (int kind = 0; kind < 2; ++kind) {
+    const int npass = kind == 0 ? 4 : hull_passes;
+    for (int d = 0; d < npass; ++d) {
+      hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
+                         kind, d, tiles, counts, h);
+      int32_t rc = exclusive_scan_i32(counts, counts, pl.count_len, partials, s);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
+                         kind, d, tiles, counts, h);
+    }
   }
-  hipLaunchKernelGGL(k_gather, dim3(eg), dim3(256), 0, s, d_xyz, vals[0], vals[1], n,
+  hipLaunchKernelGGL(k_gather, dim3(eg), dim3(256), 0, s, d_xyz, B, hid, hull_off, hull_passes, n,
                      (int4*)(ws + pl.pts), h);
   HULL_LAUNCH_CHECK();
   return HULL_OK;

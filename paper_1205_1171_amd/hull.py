@@ -20,6 +20,15 @@ HULL_EINTERNAL = -5
 _lib = None
 
 
+class Schedule(ctypes.Structure):
+    """hull_schedule_t: merge schedule of a batched call (-1 / 0 = default)."""
+    _fields_ = [("serial_levels", ctypes.c_int32), ("walk_segment", ctypes.c_int32),
+                ("fused_levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def __init__(self, serial_levels=-1, walk_segment=0, fused_levels=-1):
+        super().__init__(int(serial_levels), int(walk_segment), int(fused_levels), 0)
+
+
 class HullError(RuntimeError):
     def __init__(self, code, where=""):
         msg = _strerror(code) if _lib is not None else str(code)
@@ -52,6 +61,10 @@ def lib():
         f.restype = i32
     L.hull_full_timed.argtypes = [P, i64, P, i64, P, P, sz, P, P, i32]
     L.hull_full_timed.restype = i32
+    L.hull_workspace_bytes_batched.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    L.hull_workspace_bytes_batched.restype = i32
+    L.hull_full_batched.argtypes = [P, P, P, i64, P, i64, P, P, P, sz, ctypes.POINTER(Schedule), P]
+    L.hull_full_batched.restype = i32
     L.hull_movies.argtypes = [P, i64, i32, i32, P, P, P, P, P, sz, P]
     L.hull_movies.restype = i32
     L.hull_volume_area_fwd.argtypes = [P, P, P, P, i32, P, P, P]
@@ -66,7 +79,8 @@ def exported_symbols():
     """Names declared in include/hull3d.h that the library exports."""
     L = lib()
     names = ["hull_strerror", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
-             "hull_movies", "hull_volume_area_fwd", "hull_volume_area_bwd"]
+             "hull_workspace_bytes_batched", "hull_full_batched", "hull_movies",
+             "hull_volume_area_fwd", "hull_volume_area_bwd"]
     return [n for n in names if hasattr(L, n)]
 
 
@@ -75,6 +89,14 @@ def workspace_bytes(n, flags=0):
     rc = lib().hull_workspace_bytes(int(n), int(flags), ctypes.byref(out))
     if rc:
         raise HullError(rc, "hull_workspace_bytes")
+    return out.value
+
+
+def workspace_bytes_batched(total_points, H):
+    out = ctypes.c_size_t(0)
+    rc = lib().hull_workspace_bytes_batched(int(total_points), int(H), ctypes.byref(out))
+    if rc:
+        raise HullError(rc, "hull_workspace_bytes_batched")
     return out.value
 
 
@@ -138,6 +160,48 @@ def hull_sync(xyz, lower_only=False, ws=None):
     if st:
         raise HullError(st, "device")
     return faces[:F]
+
+
+def hull_batched(xyz, offsets, schedule=None, ws=None, faces=None, stream=None):
+    """Full hulls of H clouds in one call: cloud h is rows [offsets[h],
+    offsets[h+1]) of ``xyz``.  Returns (faces [cap, 3], face_offsets [H + 1],
+    info [2]) on the device; the faces of cloud h are rows
+    [face_offsets[h], face_offsets[h+1]), indices local to the cloud.
+    Asynchronous, like :func:`hull`."""
+    import torch
+    _check_points(xyz)
+    h_off = torch.as_tensor(offsets, dtype=torch.int64).cpu().contiguous()
+    H = h_off.numel() - 1
+    if H < 1 or int(h_off[-1]) != xyz.shape[0]:
+        raise ValueError("offsets must have H + 1 >= 2 entries ending at the point count")
+    dev = xyz.device
+    d_off = h_off.to(dev)
+    n = xyz.shape[0]
+    cap = max(2 * n, 1)
+    if faces is None:
+        faces = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+    face_off = torch.empty(H + 1, dtype=torch.int64, device=dev)
+    info = torch.empty(2, dtype=torch.int64, device=dev)
+    wbuf = (ws or Workspace()).get(workspace_bytes_batched(n, H), dev)
+    sc = ctypes.byref(schedule) if schedule is not None else None
+    rc = lib().hull_full_batched(ctypes.c_void_p(xyz.data_ptr()), ctypes.c_void_p(d_off.data_ptr()),
+                                 ctypes.c_void_p(h_off.data_ptr()), H,
+                                 ctypes.c_void_p(faces.data_ptr()), faces.shape[0],
+                                 ctypes.c_void_p(face_off.data_ptr()),
+                                 ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()),
+                                 wbuf.numel(), sc, _stream(stream))
+    if rc:
+        raise HullError(rc, "hull_full_batched")
+    return faces, face_off, info
+
+
+def hull_batched_sync(xyz, offsets, schedule=None, ws=None):
+    """Blocking call: (faces [F, 3], face_offsets [H + 1]) on the device."""
+    faces, face_off, info = hull_batched(xyz, offsets, schedule=schedule, ws=ws)
+    st, F = (int(v) for v in info.cpu())
+    if st:
+        raise HullError(st, "device")
+    return faces[:F], face_off
 
 
 def movies(xyz, run, level, ws=None):

@@ -7,8 +7,13 @@ full hull and for the lower hull, and the oracle's per-level counters of the
 bottom-up driver (events read, events written, points touched, merges) that
 define the algorithmic bytes of each merge level.
 
-usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3
-(the lower and upper runs go to two processes)
+For the batched workload cfg4 (10,000 clouds of 8 to 65,536 points) it
+records, per cloud in cloud order, the oracle's face count, and the SHA-256
+of the concatenation of every cloud's canonical face array (indices local to
+the cloud).
+
+usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3 cfg4
+(the lower and upper runs go to two processes; the clouds of cfg4 to a pool)
 """
 import hashlib
 import json
@@ -48,7 +53,44 @@ def _run(args):
     return which, f, st[which], time.time() - t
 
 
+def _cloud(q):
+    t = time.time()
+    return validate.canonical(oracle.hull(q)).astype("<i4"), time.time() - t
+
+
+def make_batched(name, workers):
+    pts, off, kinds = workloads.cfg4()
+    clouds = [pts[off[h]:off[h + 1]] for h in range(len(off) - 1)]
+    order = np.argsort([-len(c) for c in clouds], kind="stable")  # longest first
+    res = [None] * len(clouds)
+    t = time.time()
+    with ProcessPoolExecutor(workers) as ex:
+        for h, r in zip(order, ex.map(_cloud, [clouds[h] for h in order], chunksize=4)):
+            res[h] = r
+    sha = hashlib.sha256()
+    for f, _ in res:
+        sha.update(f.tobytes())
+    rec = {
+        "config": name,
+        "H": int(len(clouds)),
+        "n": int(off[-1]),
+        "input_sha256": hashlib.sha256(np.ascontiguousarray(pts, dtype="<i4").tobytes()).hexdigest(),
+        "offsets_sha256": hashlib.sha256(off.astype("<i8").tobytes()).hexdigest(),
+        "F": int(sum(len(f) for f, _ in res)),
+        "F_per_cloud": [int(len(f)) for f, _ in res],
+        "sha256_full": sha.hexdigest(),
+        "oracle_seconds_cpu": float(sum(s for _, s in res)),
+        "oracle_seconds_wall": time.time() - t,
+        "oracle_workers": workers,
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(rec, fh)
+    print(name, rec["F"], rec["oracle_seconds_cpu"], rec["oracle_seconds_wall"], flush=True)
+
+
 def make(name):
+    if name == "cfg4":
+        return make_batched(name, int(os.environ.get("GOLDEN_WORKERS", "6")))
     p = MAKERS[name]()
     with ProcessPoolExecutor(2) as ex:
         res = sorted(ex.map(_run, [(name, 0), (name, 1)]), key=lambda r: r[0])

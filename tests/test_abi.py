@@ -82,3 +82,36 @@ def test_volume_area_argument_errors(L):
     assert L.hull_volume_area_bwd(fake, fake, fake, fake, -3, fake, fake, fake, None) == hull.HULL_EINVAL
     assert L.hull_volume_area_bwd(fake, fake, None, fake, 2, fake, fake, fake, None) == hull.HULL_EINVAL
     assert L.hull_volume_area_bwd(fake, fake, fake, fake, 2, fake, fake, None, None) == hull.HULL_EINVAL
+
+
+def test_batched_argument_errors(L):
+    import numpy as np
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    info = P(0x2000)
+
+    def call(h_off, H=None, cap=None, ws=None, d_off=fake, faces=fake, face_off=fake):
+        h_off = np.asarray(h_off, dtype=np.int64)
+        H = len(h_off) - 1 if H is None else H
+        N = int(h_off[-1]) if len(h_off) else 0
+        cap = 2 * N if cap is None else cap
+        if ws is None:
+            ws = hull.workspace_bytes_batched(max(N, 0), max(H, 1))
+        return L.hull_full_batched(fake, d_off, P(h_off.ctypes.data), H, faces, cap, face_off, info,
+                                   fake, ws, None, None)
+
+    assert call([0, 10, 30], H=0) == hull.HULL_EINVAL
+    assert call([1, 10, 30]) == hull.HULL_EINVAL  # offsets[0] != 0
+    assert call([0, 20, 10]) == hull.HULL_EINVAL  # decreasing
+    assert call([0, 10, 30], cap=59) == hull.HULL_EINVAL
+    assert call([0, 10, 30], d_off=None) == hull.HULL_EINVAL
+    assert call([0, 10, 30], faces=None) == hull.HULL_EINVAL
+    assert call([0, 10, 30], face_off=None) == hull.HULL_EINVAL
+    assert call([0, (1 << 26) + 1], ws=1 << 40) == hull.HULL_EINVAL  # one cloud too large
+    ws = hull.workspace_bytes_batched(30, 2)
+    assert call([0, 10, 30], ws=ws - 1) == hull.HULL_EWORKSPACE
+    out = ctypes.c_size_t(0)
+    assert L.hull_workspace_bytes_batched(10, 0, ctypes.byref(out)) == hull.HULL_EINVAL
+    assert L.hull_workspace_bytes_batched(-1, 1, ctypes.byref(out)) == hull.HULL_EINVAL
+    # more hulls need more schedule space
+    assert hull.workspace_bytes_batched(1000, 100) > hull.workspace_bytes_batched(1000, 1)

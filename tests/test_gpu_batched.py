@@ -1,0 +1,162 @@
+"""GPU parity of the batched entry point (hull_full_batched) against the
+oracle, cloud by cloud.
+
+Every cloud's faces (indices local to the cloud, rows [face_offsets[h],
+face_offsets[h+1])) must equal the oracle's hull of that cloud alone, bit
+for bit after canonical sorting, for every merge schedule.  The full-size
+batched workload (10,000 clouds) compares against the digest that
+tests/golden/make_golden.py wrote from the oracle alone.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import validate
+from paper_1205_1171_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1205_1171_amd import hull
+    assert torch.cuda.is_available()
+    hull.lib()
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_FUSED_LEVELS"):
+        os.environ.pop(k, None)
+    return hull
+
+
+@pytest.fixture(scope="module")
+def ws(H):
+    return H.Workspace()
+
+
+# (serial_levels, walk_segment, fused_levels); -1 / 0 = library default
+SCHEDULES = {
+    "default": (-1, 0, -1),
+    "serial": (99, 0, 0),
+    "parallel": (0, 16, 0),
+    "parallel_seg8": (0, 8, 0),
+    "split3": (3, 32, 0),
+}
+
+
+def same(a, b):
+    a, b = validate.canonical(a), validate.canonical(b)
+    return a.shape == b.shape and bool((a == b).all())
+
+
+def run_batched(H, ws, clouds, sched):
+    import torch
+    sizes = [len(c) for c in clouds]
+    off = np.zeros(len(clouds) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    pts = np.concatenate([np.asarray(c, dtype=np.int32).reshape(-1, 3) for c in clouds])
+    x = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    f, fo = H.hull_batched_sync(x, off, schedule=H.Schedule(*sched), ws=ws)
+    f, fo = f.cpu().numpy(), fo.cpu().numpy()
+    assert fo[0] == 0 and fo[-1] == len(f) and (np.diff(fo) >= 0).all()
+    return [f[fo[h]:fo[h + 1]] for h in range(len(clouds))]
+
+
+def ragged_batch(rng, count):
+    clouds = []
+    for t in range(count):
+        kind = t % 8
+        n = int(rng.choice([0, 1, 2, 3, 4, 5, 8, 17, int(rng.integers(3, 400)),
+                            int(rng.integers(400, 3000))]))
+        if kind == 0:
+            p = workloads.lattice(rng, n, 1)
+        elif kind == 1:
+            p = workloads.lattice(rng, n, 5)
+        elif kind == 2:
+            p = workloads.lattice(rng, n, 5)
+            if n:
+                p[:, 0] = 3
+        elif kind == 3:
+            p = workloads.sphere(rng, n, 1 << 12) if n else np.zeros((0, 3), np.int32)
+        elif kind == 4:
+            p = workloads.ball(rng, n, 1 << 20) if n else np.zeros((0, 3), np.int32)
+        elif kind == 5:
+            p = workloads.gaussian(rng, n, sigma=6, clip=1 << 20) if n else np.zeros((0, 3), np.int32)
+        elif kind == 6:
+            p = workloads.cube(rng, n, 1 << 29) if n else np.zeros((0, 3), np.int32)
+        else:
+            q = workloads.lattice(rng, max(n // 3, 1), 4)
+            p = q[rng.integers(0, len(q), size=n)]
+        clouds.append(np.asarray(p, dtype=np.int32).reshape(-1, 3))
+    return clouds
+
+
+def oracle_faces(c):
+    return oracle.hull(c) if len(c) >= 3 else np.zeros((0, 3), np.int32)
+
+
+@pytest.mark.parametrize("name", sorted(SCHEDULES))
+def test_ragged_batch_vs_oracle(H, ws, name):
+    rng = np.random.default_rng(11)
+    for rep in range(3):
+        clouds = ragged_batch(rng, 40)
+        say("batched", name, "rep", rep, "sizes", [len(c) for c in clouds])
+        got = run_batched(H, ws, clouds, SCHEDULES[name])
+        for h, c in enumerate(clouds):
+            assert same(got[h], oracle_faces(c)), (name, rep, h, len(c))
+
+
+def test_single_cloud_batches(H, ws):
+    """H = 1 (with and without the LDS-fused bottom levels) and batches of
+    clouds that are all too small for a face."""
+    rng = np.random.default_rng(5)
+    p = workloads.cube(rng, 5000, 1 << 20)
+    for sched in ((-1, 0, 0), (8, 0, 7), (9, 0, 9), (0, 8, 0)):
+        say("single cloud batch", sched)
+        got = run_batched(H, ws, [p], sched)
+        assert same(got[0], oracle.hull(p))
+    say("tiny clouds")
+    tiny = [np.zeros((k % 3, 3), np.int32) + k for k in range(30)]
+    got = run_batched(H, ws, tiny, (-1, 0, -1))
+    assert all(len(f) == 0 for f in got)
+
+
+def test_batched_equals_subset_of_cfg4(H, ws):
+    """The first clouds of the batched workload (same generator, smaller
+    sizes), each against the oracle."""
+    pts, off, _ = workloads.cfg4(H=200, lo=3.0, hi=11.0)
+    clouds = [pts[off[h]:off[h + 1]] for h in range(len(off) - 1)]
+    say("cfg4 subset", len(clouds), int(off[-1]))
+    got = run_batched(H, ws, clouds, (-1, 0, -1))
+    for h, c in enumerate(clouds):
+        assert same(got[h], oracle.hull(c)), h
+
+
+def test_cfg4_full_digest(H, ws):
+    """All 10,000 clouds of the batched workload in one call, in the launch
+    configuration the benchmark times: digest of every cloud's canonical
+    faces, in cloud order, against the oracle's."""
+    import torch
+    path = os.path.join(GOLDEN, "cfg4.json")
+    rec = json.load(open(path))
+    pts, off, _ = workloads.cfg4()
+    assert hashlib.sha256(np.ascontiguousarray(pts, dtype="<i4").tobytes()).hexdigest() == rec["input_sha256"]
+    say("cfg4 full", len(off) - 1, int(off[-1]))
+    x = torch.from_numpy(pts).cuda()
+    f, fo = H.hull_batched_sync(x, off, ws=ws)
+    f, fo = f.cpu().numpy(), fo.cpu().numpy()
+    counts = np.diff(fo)
+    assert counts.tolist() == rec["F_per_cloud"]
+    sha = hashlib.sha256()
+    for h in range(len(off) - 1):
+        sha.update(validate.canonical(f[fo[h]:fo[h + 1]]).astype("<i4").tobytes())
+    assert sha.hexdigest() == rec["sha256_full"]
