@@ -88,8 +88,8 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
  * takes the library default):
  *   serial_levels  merge levels 1..serial_levels run one lane per merge (the
  *                  paper's kernel, Sec. 3); the levels above split each merge
- *                  into time segments walked in parallel (default 10)
- *   walk_segment   child events per walk segment, >= 8 (default 16)
+ *                  into time segments walked in parallel (default 9)
+ *   walk_segment   child events per walk segment, >= 8 (default 8)
  *   fused_levels   0, or 7..9: the bottom levels of a single hull merged in
  *                  LDS tiles of 2^fused_levels points (default 0) */
 typedef struct hull_schedule_t {

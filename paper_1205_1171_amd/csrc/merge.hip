@@ -82,99 +82,169 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   }
   const int u0 = u, v0 = v;
 
-  // 2. event loop
+  // 2. event loop.  Candidates: the next L event, the next R event and the
+  // four bridge moves: nx(u) enters (u, nx u, v), u leaves (pv u, u, v),
+  // pv(v) enters (u, pv v, v), v leaves (u, v, nx v).  A child event is
+  // always later than the last event T (it follows T in its own movie, or T
+  // was chosen before it), so only the bridge moves are checked against T.
+  // The bridge moves, their validity (strictly after T) and the earliest of
+  // them depend only on u, v and the four links, so they are recomputed only
+  // when one of those changes; a valid move not taken stays after T, an
+  // invalid one stays before it.
   int i = 0, j = 0, k = 0;
   bool haveT = false;
   Cand T;
   T.t = Tri{-1, -1, -1};
   T.st = 0.0;
   T.kind = 0;
+  int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
+  // bridge best: slot (2..5, -1 = none) and its standard part
+  int bbi = -1;
+  double bbs = 0.0;
+  double st2 = 0.0, st3 = 0.0, st4 = 0.0, st5 = 0.0;
+  bool ok2 = false, ok3 = false, ok4 = false, ok5 = false;
+  unsigned dirty = 0xF;
   const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
   for (int64_t it = 0;; ++it) {
     if (it > iter_cap) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
       break;
     }
-    // candidates: 0 next L event, 1 next R event, 2..5 bridge moves.  The
-    // running best is kept field by field in scalars, every candidate index
-    // is a compile-time constant: the candidates stay in registers.
+    if (dirty) {
+#define HULL_SLOT(BIT, OK, ST, LINK, A, W, B, PA, PW, PB, KIND)            \
+  if (dirty & (BIT)) {                                                   \
+    OK = (LINK) != kNil;                                                 \
+    if (OK) {                                                            \
+      const Cand c_ = make_cand(pts, A, W, B, PA, PW, PB, KIND, zs);     \
+      ST = c_.st;                                                        \
+      OK = !haveT || ev_cmp(pts, c_, T, zs) > 0;                         \
+    }                                                                    \
+  }
+      HULL_SLOT(1u, ok2, st2, nu, u, nu, v, Pu, pts[nu], Pv, 1)
+      HULL_SLOT(2u, ok3, st3, pu, pu, u, v, pts[pu], Pu, Pv, 0)
+      HULL_SLOT(4u, ok4, st4, pvv, u, pvv, v, Pu, pts[pvv], Pv, 1)
+      HULL_SLOT(8u, ok5, st5, nv, u, v, nv, Pu, Pv, pts[nv], 0)
+#undef HULL_SLOT
+      // earliest valid bridge move, slots in a fixed order
+      bbi = -1;
+      int ba = 0, bw = 0, bb = 0, bk = 0;
+#define HULL_BRIDGE(IDX, OK, ST, A, W, B, KIND)                            \
+  if (OK) {                                                              \
+    bool take_ = bbi < 0;                                                \
+    if (!take_) {                                                        \
+      Cand x_, y_;                                                       \
+      x_.t = Tri{A, W, B};                                               \
+      x_.st = ST;                                                        \
+      x_.kind = KIND;                                                    \
+      y_.t = Tri{ba, bw, bb};                                            \
+      y_.st = bbs;                                                       \
+      y_.kind = bk;                                                      \
+      take_ = ev_cmp(pts, x_, y_, zs) < 0;                               \
+    }                                                                    \
+    if (take_) {                                                         \
+      bbi = (IDX);                                                       \
+      ba = A;                                                            \
+      bw = W;                                                            \
+      bb = B;                                                            \
+      bk = KIND;                                                         \
+      bbs = ST;                                                          \
+    }                                                                    \
+  }
+      HULL_BRIDGE(2, ok2, st2, u, nu, v, 1)
+      HULL_BRIDGE(3, ok3, st3, pu, u, v, 0)
+      HULL_BRIDGE(4, ok4, st4, u, pvv, v, 1)
+      HULL_BRIDGE(5, ok5, st5, u, v, nv, 0)
+#undef HULL_BRIDGE
+      dirty = 0;
+    }
+    // the bridge best as a candidate
     int bi = -1, ba = 0, bw = 0, bb = 0, bk = 0;
-    double bs = 0.0;
-#define HULL_CONSIDER(IDX, CAND)                                                  \
-  do {                                                                            \
-    const Cand cc_ = (CAND);                                                      \
-    bool take_ = !(haveT && ev_cmp(pts, cc_, T, zs) <= 0);                        \
-    if (take_ && bi >= 0) {                                                       \
-      Cand cb_;                                                                   \
-      cb_.t = Tri{ba, bw, bb};                                                    \
-      cb_.st = bs;                                                                \
-      cb_.kind = bk;                                                              \
-      take_ = ev_cmp(pts, cc_, cb_, zs) < 0;                                      \
-    }                                                                             \
-    if (take_) {                                                                  \
-      bi = (IDX);                                                                 \
-      ba = cc_.t.a;                                                               \
-      bw = cc_.t.w;                                                               \
-      bb = cc_.t.b;                                                               \
-      bs = cc_.st;                                                                \
-      bk = cc_.kind;                                                              \
-    }                                                                             \
-  } while (0)
-    if (i < nL) {
-      Event E = Lev[i];
-      Cand c;
-      c.t = Tri{E.a, E.w, E.b};
-      c.kind = E.kind;
-      c.st = Ltau[i];
-      HULL_CONSIDER(0, c);
+    double bs = bbs;
+    if (bbi >= 0) {
+      bi = bbi;
+      if (bbi == 2) { ba = u; bw = nu; bb = v; bk = 1; }
+      else if (bbi == 3) { ba = pu; bw = u; bb = v; bk = 0; }
+      else if (bbi == 4) { ba = u; bw = pvv; bb = v; bk = 1; }
+      else { ba = u; bw = v; bb = nv; bk = 0; }
     }
-    if (j < nR) {
-      Event E = Rev[j];
-      Cand c;
-      c.t = Tri{E.a, E.w, E.b};
-      c.kind = E.kind;
-      c.st = Rtau[j];
-      HULL_CONSIDER(1, c);
-    }
-    const int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
-    if (nu != kNil) HULL_CONSIDER(2, make_cand(pts, u, nu, v, Pu, pts[nu], Pv, 1, zs));
-    if (pu != kNil) HULL_CONSIDER(3, make_cand(pts, pu, u, v, pts[pu], Pu, Pv, 0, zs));
-    if (pvv != kNil) HULL_CONSIDER(4, make_cand(pts, u, pvv, v, Pu, pts[pvv], Pv, 1, zs));
-    if (nv != kNil) HULL_CONSIDER(5, make_cand(pts, u, v, nv, Pu, Pv, pts[nv], 0, zs));
-#undef HULL_CONSIDER
+#define HULL_CHILD(IDX, EV, TAU, Q)                                        \
+  {                                                                      \
+    const Event E_ = (EV)[Q];                                            \
+    const double t_ = (TAU)[Q];                                          \
+    bool take_ = bi < 0;                                                 \
+    if (!take_) {                                                        \
+      Cand x_, y_;                                                       \
+      x_.t = Tri{E_.a, E_.w, E_.b};                                      \
+      x_.st = t_;                                                        \
+      x_.kind = E_.kind;                                                 \
+      y_.t = Tri{ba, bw, bb};                                            \
+      y_.st = bs;                                                        \
+      y_.kind = bk;                                                      \
+      take_ = ev_cmp(pts, x_, y_, zs) < 0;                               \
+    }                                                                    \
+    if (take_) {                                                         \
+      bi = (IDX);                                                        \
+      ba = E_.a;                                                         \
+      bw = E_.w;                                                         \
+      bb = E_.b;                                                         \
+      bs = t_;                                                           \
+    }                                                                    \
+  }
+    if (i < nL) HULL_CHILD(0, Lev, Ltau, i)
+    if (j < nR) HULL_CHILD(1, Rev, Rtau, j)
+#undef HULL_CHILD
     if (bi < 0) break;
+    // the kind of the chosen event, from its source once the choice is made
+    // (not carried through the selection: hipcc for gfx950 has dropped the
+    // condition on such a carried field, taking the old value for lanes that
+    // switch candidates)
+    if (bi == 0) bk = Lev[i].kind;
+    else if (bi == 1) bk = Rev[j].kind;
+    else bk = (bi == 2 || bi == 4) ? 1 : 0;
     T.t = Tri{ba, bw, bb};
     T.st = bs;
     T.kind = bk;
     haveT = true;
     bool emit = false;
     if (bi <= 1) {
-      const Tri& t = T.t;
-      emit = bi == 0 ? (t.w < u) : (t.w > v);
-      if (T.kind) {  // insertion into the child's chain
-        nx[t.a] = t.w;
-        pv[t.b] = t.w;
-        pv[t.w] = t.a;
-        nx[t.w] = t.b;
+      emit = bi == 0 ? (bw < u) : (bw > v);
+      if (bk) {  // insertion into the child's chain
+        nx[ba] = bw;
+        pv[bb] = bw;
+        pv[bw] = ba;
+        nx[bw] = bb;
       } else {  // deletion
-        nx[t.a] = t.b;
-        pv[t.b] = t.a;
+        nx[ba] = bb;
+        pv[bb] = ba;
       }
       if (bi == 0) ++i; else ++j;
+      // a link of u or v may have changed
+      const int nu2 = nx[u], pu2 = pv[u], pv2 = pv[v], nv2 = nx[v];
+      dirty = (nu2 != nu ? 1u : 0u) | (pu2 != pu ? 2u : 0u) | (pv2 != pvv ? 4u : 0u) |
+              (nv2 != nv ? 8u : 0u);
+      nu = nu2;
+      pu = pu2;
+      pvv = pv2;
+      nv = nv2;
     } else {
       emit = true;
       if (bi == 2) { u = nu; Pu = pts[u]; }
       else if (bi == 3) { u = pu; Pu = pts[u]; }
       else if (bi == 4) { v = pvv; Pv = pts[v]; }
       else { v = nv; Pv = pts[v]; }
+      nu = nx[u];
+      pu = pv[u];
+      pvv = pv[v];
+      nv = nx[v];
+      dirty = 0xF;
     }
     if (emit) {
       if (k >= cap) {
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      out[k] = Event{T.t.a, T.t.w, T.t.b, T.kind};
-      out_tau[k] = T.st;
+      out[k] = Event{ba, bw, bb, bk};
+      out_tau[k] = bs;
       ++k;
     }
   }
@@ -498,8 +568,8 @@ struct Opts {
 
 static Opts resolve(const hull_schedule_t* sc) {
   Opts o;
-  o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 10);
-  o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 16);
+  o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 9);
+  o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 8);
   if (o.seg < 8) o.seg = 8;
   o.fused = sc && sc->fused_levels >= 0 ? sc->fused_levels : env_int("HULL_FUSED_LEVELS", 0);
   if (o.fused > 0) o.fused = o.fused < 7 ? 7 : (o.fused > 9 ? 9 : o.fused);

@@ -364,27 +364,78 @@ __global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
   }
 }
 
-// One list per touched (point, side), allocated by whichever event claims it
-// first at this level.
-__device__ __forceinline__ void claim(const ParRun& R, int p, int side, int stamp) {
-  int* cl = side ? R.claimL : R.claimR;
-  if (atomicExch(&cl[p], stamp) == stamp) return;
-  int* off = side ? R.offL : R.offR;
-  const int* cnt = side ? R.cntL : R.cntR;
-  off[p] = atomicAdd(&R.ctr[side], cnt[p]);
-  R.touched[atomicAdd(&R.ctr[2], 1)] = (p << 1) | side;
+// Inclusive prefix sum over the 64 lanes of a wavefront (every lane takes
+// part).
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
 }
 
+// One list per touched (point, side), allocated by whichever event claims it
+// first at this level (claim stamp = the level).  The list space is handed
+// out per wavefront: one atomic per wavefront and counter, each claim's
+// offset from the wavefront's prefix sums.
 __global__ void __launch_bounds__(256) k_par_alloc(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  GRID_STRIDE(c, R.ctr[5]) {
-    const Event X = R.ev_in[R.cslot[c]];
-    claim(R, X.a, 0, R.stamp);
-    claim(R, X.b, 1, R.stamp);
-    if (X.kind) {
-      claim(R, X.w, 0, R.stamp);
-      claim(R, X.w, 1, R.stamp);
+  const int E = R.ctr[5], st = R.stamp;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // capacities: 4n entries per side (at most 2 per child event, 2n events),
+  // 2n touched lists (one per point and side)
+  const int64_t ent_cap = 2 * (int64_t)P.ecap, touched_cap = P.ecap;
+  // the loop bound is the same for the 64 lanes of a wavefront
+  for (int64_t w0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); w0 < E; w0 += stride) {
+    const int64_t c = w0 + lane;
+    int pR0 = kNil, pR1 = kNil, pL0 = kNil, pL1 = kNil;
+    if (c < E) {
+      const Event X = R.ev_in[R.cslot[c]];
+      if (atomicExch(&R.claimR[X.a], st) != st) pR0 = X.a;
+      if (atomicExch(&R.claimL[X.b], st) != st) pL0 = X.b;
+      if (X.kind) {
+        if (atomicExch(&R.claimR[X.w], st) != st) pR1 = X.w;
+        if (atomicExch(&R.claimL[X.w], st) != st) pL1 = X.w;
+      }
+    }
+    const int cR0 = pR0 != kNil ? R.cntR[pR0] : 0, cR1 = pR1 != kNil ? R.cntR[pR1] : 0;
+    const int cL0 = pL0 != kNil ? R.cntL[pL0] : 0, cL1 = pL1 != kNil ? R.cntL[pL1] : 0;
+    const int nT = (pR0 != kNil) + (pR1 != kNil) + (pL0 != kNil) + (pL1 != kNil);
+    const int iR = wave_incl_scan(cR0 + cR1), iL = wave_incl_scan(cL0 + cL1),
+              iT = wave_incl_scan(nT);
+    const int tR = __shfl(iR, 63, 64), tL = __shfl(iL, 63, 64), tT = __shfl(iT, 63, 64);
+    int bR = 0, bL = 0, bT = 0;
+    if (lane == 0) {
+      if (tR) bR = atomicAdd(&R.ctr[0], tR);
+      if (tL) bL = atomicAdd(&R.ctr[1], tL);
+      if (tT) bT = atomicAdd(&R.ctr[2], tT);
+    }
+    bR = __shfl(bR, 0, 64) + iR - (cR0 + cR1);
+    bL = __shfl(bL, 0, 64) + iL - (cL0 + cL1);
+    bT = __shfl(bT, 0, 64) + iT - nT;
+    if (bR + cR0 + cR1 > ent_cap || bL + cL0 + cL1 > ent_cap || bT + nT > touched_cap) {
+      atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+      continue;
+    }
+    if (pR0 != kNil) {
+      R.offR[pR0] = bR;
+      R.touched[bT++] = pR0 << 1;
+    }
+    if (pR1 != kNil) {
+      R.offR[pR1] = bR + cR0;
+      R.touched[bT++] = pR1 << 1;
+    }
+    if (pL0 != kNil) {
+      R.offL[pL0] = bL;
+      R.touched[bT++] = (pL0 << 1) | 1;
+    }
+    if (pL1 != kNil) {
+      R.offL[pL1] = bL + cL0;
+      R.touched[bT++] = (pL1 << 1) | 1;
     }
   }
 }
@@ -393,7 +444,7 @@ __global__ void __launch_bounds__(256) k_par_alloc(ParLevel P) {
 // field also carries its slot, kind | slot << 1, the sort key) and its time.
 __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts) return;
+  if (!R.pts || P.h->err) return;  // after an error the offsets may be stale
   GRID_STRIDE(c, R.ctr[5]) {
     const int q = R.cslot[c];
     const Event E = R.ev_in[q];
@@ -418,7 +469,7 @@ __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
 
 __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts) return;
+  if (!R.pts || P.h->err) return;
   GRID_STRIDE(t, R.ctr[2]) {
     const int x = R.touched[t], p = x >> 1;
     if (x & 1) sort_entries(R.entL + R.offL[p], R.entLt + R.offL[p], R.cntL[p]);
