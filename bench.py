@@ -5,16 +5,27 @@ level of the lower and upper runs, face extraction) on the n = 2^24 workload
 (99% Gaussian, 1% sphere), inputs resident in HBM.  Prints one JSON line:
 value = Mpoints/s = n / (time per step).
 
-Also reported:
-  roofline      the merge-level kernel: algorithmic bytes per launch (from the
-                oracle's per-level counters: 4 B per event read, 4 B per
-                event written, 28 B per point touched) over its average launch
-                time, measured with HIP events recorded around every merge
-                launch on the library's stream during the timed steps;
-  cpu_baseline  the oracle (sequential C, one thread) on a bounded sample of
-                the same workload.
+Also reported on the same line:
+  roofline        the lane-serial merge kernel (k_merge_level, the largest
+                  share of the step): algorithmic bytes per launch (from the
+                  oracle's per-level counters: 4 B per event read, 4 B per
+                  event written, 28 B per point touched) over its average
+                  launch time, measured with HIP events recorded around each
+                  of its launches on the library's stream in the timed steps;
+  levels          the same figure for every merge level (the parallel levels
+                  are several kernels each, timed as a whole);
+  batched         10,000 ragged clouds (7.3e7 points) in one hull_full_batched
+                  call captured in a HIP graph, against one hull_full launch
+                  per cloud on the same stream (hulls/s), schedule from the
+                  autotuner's cache;
+  differentiation 256 clouds x 16,384 points: FP32 volume/area forward +
+                  backward for all clouds in one launch each, against one
+                  launch per cloud, with and without the batched hull first;
+  cpu_baseline    the oracle (sequential C, one thread) on a bounded sample of
+                  the n = 2^24 workload.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
+                       [--no-batched] [--no-diff] [--no-cpu]
 """
 import argparse
 import ctypes
@@ -28,6 +39,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def _hip():
@@ -70,6 +85,20 @@ def levels_for(n):
     return L
 
 
+def timed(fn, reps):
+    """Average ms of fn() over reps calls, timed with events on torch's
+    current stream (where the library launches)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def cpu_baseline(p, sample_n):
     """The oracle, as it stands, on the first sample_n rows (rows are in
     random order, so this is a uniform subsample of the same workload)."""
@@ -80,45 +109,31 @@ def cpu_baseline(p, sample_n):
     dt = time.perf_counter() - t
     return {"value": round(sample_n / dt / 1e6, 6), "unit": "Mpoints/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"first {sample_n} rows of the workload (uniform subsample), lower+upper "
-                      f"runs, sequential C oracle, {dt:.1f} s, {len(f)} faces"}
+            "sample": f"first {sample_n} rows of the n = 2^24 workload (a uniform subsample), "
+                      f"lower+upper runs, sequential C oracle on one thread, {dt:.1f} s, "
+                      f"{len(f)} faces"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg3")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 17)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hull is not "
-              "distributed across GPUs.", file=sys.stderr)
-        sys.exit(2)
-
+def single(args, hull, workloads):
     import numpy as np
     import torch
-
-    from paper_1205_1171_amd import hull, workloads
     L_ = hull.lib()
     maker = {"cfg1": workloads.cfg1, "cfg2_sphere": workloads.cfg2_sphere,
              "cfg2_ball": workloads.cfg2_ball, "cfg3": workloads.cfg3}[args.workload]
     p = maker()
     n = len(p)
-    print(f"[bench] workload {args.workload} n={n}", file=sys.stderr, flush=True)
+    log(f"workload {args.workload} n={n}")
     dev = torch.device("cuda:0")
     x = torch.from_numpy(p).to(dev)
     cap = 2 * n
     faces = torch.empty((cap, 3), dtype=torch.int32, device=dev)
     info = torch.zeros(2, dtype=torch.int64, device=dev)
     ws = torch.empty(hull.workspace_bytes(n), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    sptr = ctypes.c_void_p(stream.cuda_stream)
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     L = levels_for(n)
     nev = 2 * L + 3
     ev = Events(nev * max(args.steps, 1))
+    sched = hull.schedule_defaults()
 
     def step(k=None):
         if k is None:
@@ -138,7 +153,7 @@ def main():
     for w in range(args.warmup):
         step()
         torch.cuda.synchronize()
-        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+        log(f"warmup {w} done")
     st, F = (int(v) for v in info.cpu())
     if st:
         raise hull.HullError(st, "device")
@@ -159,10 +174,10 @@ def main():
         step(k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
+    log(f"timed {args.steps} steps")
     ms = (t1 - t0) * 1000.0 / args.steps
 
-    # per-level merge kernel times (ms), averaged over the timed steps
+    # per-level merge times (ms), averaged over the timed steps
     lvl = np.zeros(L)
     sort_ms = extract_ms = 0.0
     for k in range(args.steps):
@@ -176,25 +191,35 @@ def main():
     extract_ms /= args.steps
     ev.close()
 
-    roofline = None
+    roofline = levels = None
+    S = min(sched.serial_levels, L) if sched.fused_levels == 0 else 0
     if golden is not None:
         stats = np.array(golden["level_stats_lower"]) + np.array(golden["level_stats_upper"])
-        Bk = 4 * stats[:, 0] + 4 * stats[:, 1] + 28 * stats[:, 2]   # bytes per level
-        per_launch = float(Bk.sum()) / L
-        avg_s = float(lvl.mean()) / 1000.0
-        achieved = per_launch / avg_s / 1e9
-        traffic = None
-        tpath = os.path.join(ROOT, "profiles", f"merge_level_{args.workload}_traffic.json")
-        if os.path.exists(tpath):
-            tr = json.load(open(tpath))
-            src = open(os.path.join(ROOT, "paper_1205_1171_amd", "csrc", "merge.hip"), "rb").read()
-            if tr.get("merge_source_sha256") == hashlib.sha256(src).hexdigest():
-                traffic = tr.get("bytes_per_launch")
-        roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
-                    "kernel": "k_merge_level", "launches_per_step": L,
-                    "avg_launch_ms": round(float(lvl.mean()), 4),
-                    "algorithmic_bytes_per_launch": per_launch}
+        Bk = 4.0 * stats[:, 0] + 4.0 * stats[:, 1] + 28.0 * stats[:, 2]  # bytes per level
+        levels = [{"level": k + 1, "kernel": "k_merge_level" if k < S else "parallel (13 kernels)",
+                   "ms": round(float(lvl[k]), 4), "algorithmic_bytes": float(Bk[k]),
+                   "GBps": round(float(Bk[k]) / (lvl[k] / 1e3) / 1e9, 2),
+                   "frac": round(float(Bk[k]) / (lvl[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 6)}
+                  for k in range(L)]
+        if S > 0:
+            per_launch = float(Bk[:S].sum()) / S
+            avg_ms = float(lvl[:S].mean())
+            achieved = per_launch / (avg_ms / 1e3) / 1e9
+            traffic = None
+            tpath = os.path.join(ROOT, "profiles", f"k_merge_level_{args.workload}_traffic.json")
+            if os.path.exists(tpath):
+                tr = json.load(open(tpath))
+                src = b"".join(open(os.path.join(ROOT, "paper_1205_1171_amd", "csrc", f), "rb").read()
+                               for f in ("merge.hip", "events.hpp", "predicates.hpp"))
+                if (tr.get("source_sha256") == hashlib.sha256(src).hexdigest()
+                        and tr.get("serial_levels") == S):
+                    traffic = tr.get("hbm_bytes_per_launch")
+            roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                        "traffic": traffic, "kernel": "k_merge_level",
+                        "launches_per_step": S, "avg_launch_ms": round(avg_ms, 4),
+                        "algorithmic_bytes_per_launch": per_launch,
+                        "all_levels_GBps": round(float(Bk.sum()) / (lvl.sum() / 1e3) / 1e9, 3)}
 
     out = {
         "metric": "Mpoints/s per hull (n=2^24)",
@@ -209,16 +234,209 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={n}", "n": n, "faces": F,
-                   "runs": "lower+upper"},
+        "config": {"workload": f"{args.workload}: n={n} (99% Gaussian sigma 2^16 clipped to "
+                               f"+-2^20, 1% sphere radius 2^20)" if args.workload == "cfg3"
+                   else f"{args.workload}: n={n}",
+                   "n": n, "faces": F, "runs": "lower+upper",
+                   "schedule": {"serial_levels": sched.serial_levels,
+                                "walk_segment": sched.walk_segment,
+                                "fused_levels": sched.fused_levels}},
         "bit_exact": bit_exact,
         "phase_ms": {"sort": round(sort_ms, 4), "merge_levels": [round(v, 4) for v in lvl],
                      "extract": round(extract_ms, 4)},
         "roofline": roofline,
+        "levels": levels,
     }
+    return out, p
+
+
+def batched(hull, workloads, autotune, reps):
+    """cfg4: one graph-captured batched call against one call per cloud."""
+    import numpy as np
+    import torch
+    L_ = hull.lib()
+    pts, off, _ = workloads.cfg4()
+    H = len(off) - 1
+    N = int(off[-1])
+    log(f"batched workload: {H} clouds, {N} points")
+    x = torch.from_numpy(pts).cuda()
+    sched = autotune.lookup(off)
+    bh = hull.BatchedHull(x, off, sched)
+    bh.run()
+    faces, face_off = bh.result()
+    bit_exact = None
+    gpath = os.path.join(ROOT, "tests", "golden", "cfg4.json")
+    if os.path.exists(gpath):
+        from oracle import validate
+        rec = json.load(open(gpath))
+        f = faces.cpu().numpy()
+        fo = face_off.cpu().numpy()
+        sha = hashlib.sha256()
+        for h in range(H):
+            sha.update(validate.canonical(f[fo[h]:fo[h + 1]]).astype("<i4").tobytes())
+        bit_exact = (np.diff(fo).tolist() == rec["F_per_cloud"]
+                     and sha.hexdigest() == rec["sha256_full"])
+    log(f"batched bit_exact={bit_exact}")
+    ms_eager = timed(bh.run, reps)
+    bh.capture()
+    bh.replay()
+    ms_graph = timed(bh.replay, reps)
+    log(f"batched graph {ms_graph:.2f} ms, eager {ms_eager:.2f} ms")
+
+    # one hull_full call per cloud, same stream, one workspace for the largest
+    sizes = np.diff(off)
+    nmax = int(sizes.max())
+    ws = torch.empty(hull.workspace_bytes(nmax), dtype=torch.uint8, device="cuda")
+    fbuf = torch.empty((2 * nmax, 3), dtype=torch.int32, device="cuda")
+    info = torch.zeros(2, dtype=torch.int64, device="cuda")
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    base = x.data_ptr()
+
+    def per_hull(count):
+        for h in range(count):
+            rc = L_.hull_full(ctypes.c_void_p(base + 12 * int(off[h])), int(sizes[h]),
+                              ctypes.c_void_p(fbuf.data_ptr()), fbuf.shape[0],
+                              ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), sptr)
+            if rc:
+                raise hull.HullError(rc, "hull_full")
+
+    per_hull(min(H, 200))  # warm-up
+    ms_loop = timed(lambda: per_hull(H), 1)
+    log(f"one launch per cloud: {ms_loop:.1f} ms")
+    s = sched if sched is not None else hull.schedule_defaults()
+    return {
+        "workload": f"cfg4: {H} clouds, sizes floor(2^U), U ~ U[3,16], 50/50 ball/sphere of "
+                    f"radius 2^20, {N} points",
+        "hulls": H, "points": N, "faces": int(face_off[-1]),
+        "schedule": {"serial_levels": s.serial_levels, "walk_segment": s.walk_segment,
+                     "source": "autotuner cache" if sched is not None else "library defaults"},
+        "ms_graph": round(ms_graph, 3), "ms_eager": round(ms_eager, 3),
+        "ms_one_launch_per_hull": round(ms_loop, 3),
+        "hulls_per_s": round(H / (ms_graph / 1e3), 1),
+        "hulls_per_s_eager": round(H / (ms_eager / 1e3), 1),
+        "hulls_per_s_one_launch_per_hull": round(H / (ms_loop / 1e3), 1),
+        "speedup_vs_one_launch_per_hull": round(ms_loop / ms_graph, 2),
+        "Mpoints_per_s": round(N / (ms_graph / 1e3) / 1e6, 2),
+        "bit_exact": bit_exact,
+    }
+
+
+def differentiation(hull, workloads, autotune, reps):
+    """cfg5: FP32 volume/area forward + backward, batched against per cloud."""
+    import numpy as np
+    import torch
+    P, Q = workloads.cfg5()
+    B, m = P.shape[0], P.shape[1]
+    log(f"differentiation workload: {B} clouds x {m} points")
+    p = torch.from_numpy(P.reshape(-1, 3)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(Q.reshape(-1, 3))).cuda()
+    off = np.arange(0, B * m + 1, m, dtype=np.int64)
+    d_off = torch.from_numpy(off).cuda()
+    bh = hull.BatchedHull(x, off, autotune.lookup(off))
+    bh.run()
+    faces, face_off = bh.result()
+    faces = faces.contiguous()
+    gV = torch.ones(B, dtype=torch.float32, device="cuda")
+    gA = torch.ones(B, dtype=torch.float32, device="cuda")
+
+    def fb_batched():
+        hull.volume_area_fwd(p, d_off, faces, face_off)
+        hull.volume_area_bwd(p, d_off, faces, face_off, gV, gA)
+
+    fo = face_off.cpu().numpy()
+    one_off = torch.tensor([0, m], dtype=torch.int64, device="cuda")
+    cloud_face_off = [torch.tensor([0, int(fo[b + 1] - fo[b])], dtype=torch.int64, device="cuda")
+                      for b in range(B)]
+    L_ = hull.lib()
+    Vb = torch.empty(1, dtype=torch.float32, device="cuda")
+    Ab = torch.empty(1, dtype=torch.float32, device="cuda")
+    g = torch.empty((m, 3), dtype=torch.float32, device="cuda")
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P_ = ctypes.c_void_p
+
+    def fb_cloud(b):
+        pp = P_(p.data_ptr() + 12 * b * m)
+        ff = P_(faces.data_ptr() + 12 * int(fo[b]))
+        rc = L_.hull_volume_area_fwd(pp, P_(one_off.data_ptr()), ff,
+                                     P_(cloud_face_off[b].data_ptr()), 1, P_(Vb.data_ptr()),
+                                     P_(Ab.data_ptr()), sptr)
+        rc = rc or L_.hull_volume_area_bwd(pp, P_(one_off.data_ptr()), ff,
+                                           P_(cloud_face_off[b].data_ptr()), 1,
+                                           P_(gV.data_ptr()), P_(gA.data_ptr()),
+                                           P_(g.data_ptr()), sptr)
+        if rc:
+            raise hull.HullError(rc, "volume/area")
+
+    def fb_per_cloud():
+        for b in range(B):
+            fb_cloud(b)
+
+    ws = torch.empty(hull.workspace_bytes(m), dtype=torch.uint8, device="cuda")
+    fbuf = torch.empty((2 * m, 3), dtype=torch.int32, device="cuda")
+    info = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+    def hull_fb_per_cloud():
+        for b in range(B):
+            rc = L_.hull_full(P_(x.data_ptr() + 12 * b * m), m, P_(fbuf.data_ptr()), fbuf.shape[0],
+                              P_(info.data_ptr()), P_(ws.data_ptr()), ws.numel(), sptr)
+            if rc:
+                raise hull.HullError(rc, "hull_full")
+            fb_cloud(b)
+
+    def hull_fb_batched():
+        bh.run()
+        fb_batched()
+
+    fb_batched()
+    fb_per_cloud()
+    ms_b = timed(fb_batched, reps)
+    ms_c = timed(fb_per_cloud, reps)
+    hull_fb_per_cloud()
+    ms_hb = timed(hull_fb_batched, reps)
+    ms_hc = timed(hull_fb_per_cloud, 1)
+    V, A = hull.volume_area_fwd(p, d_off, faces, face_off)
+    ok = bool(torch.isfinite(V).all() and torch.isfinite(A).all() and (V > 0).all())
+    log(f"fwd+bwd batched {ms_b:.3f} ms, per cloud {ms_c:.3f} ms")
+    return {
+        "workload": f"cfg5: {B} clouds x {m} points on a sphere of radius 2^18 with radial "
+                    f"noise sigma 2^10, FP32",
+        "clouds": B, "faces": int(fo[-1]),
+        "ms_fwd_bwd_batched": round(ms_b, 4), "ms_fwd_bwd_one_launch_per_cloud": round(ms_c, 4),
+        "speedup_fwd_bwd": round(ms_c / ms_b, 2),
+        "ms_hull_fwd_bwd_batched": round(ms_hb, 3),
+        "ms_hull_fwd_bwd_one_launch_per_cloud": round(ms_hc, 3),
+        "speedup_with_hull": round(ms_hc / ms_hb, 2),
+        "finite_positive_volumes": ok,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hull is not "
+              "distributed across GPUs.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1205_1171_amd import autotune, hull, workloads
+    hull.lib()
+    out, p = single(args, hull, workloads)
+    if not args.no_batched:
+        out["batched"] = batched(hull, workloads, autotune, reps=3)
+    if not args.no_diff:
+        out["differentiation"] = differentiation(hull, workloads, autotune, reps=5)
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(p, min(args.cpu_sample, n))
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(p, min(args.cpu_sample, len(p)))
     print(json.dumps(out), flush=True)
 
 

@@ -29,6 +29,9 @@
  *    per orientation.
  *  - Calls on different streams are independent if each has its own
  *    workspace.
+ *  - A HIP error left pending on the calling thread by earlier, unrelated
+ *    HIP calls is cleared on entry (it is not reported as this call's
+ *    failure); hull_last_hip_error() gives the HIP code behind a HULL_EHIP.
  */
 #ifndef HULL3D_H
 #define HULL3D_H
@@ -50,6 +53,10 @@ extern "C" {
 
 /* Static description of a status code. */
 const char* hull_strerror(int32_t code);
+
+/* The hipError_t behind the last HULL_EHIP returned on this host thread (0
+ * if none yet). */
+int32_t hull_last_hip_error(void);
 
 /* Bytes of device workspace that hull_lower / hull_full need for n points
  * (host, synchronous).  flags: reserved, pass 0. */
@@ -98,6 +105,12 @@ typedef struct hull_schedule_t {
   int32_t fused_levels;
   int32_t reserved;
 } hull_schedule_t;
+
+/* The schedule the library uses when a call passes none (or leaves a field
+ * at its default): the built-in defaults, overridden by the environment
+ * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT and HULL_FUSED_LEVELS when
+ * set.  Host, synchronous. */
+int32_t hull_schedule_defaults(hull_schedule_t* out);
 
 /* Bytes of device workspace for hull_full_batched over H hulls of
  * total_points points in all (host, synchronous). */

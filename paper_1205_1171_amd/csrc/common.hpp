@@ -59,11 +59,22 @@ struct Plan {
 // min_seg: the smallest walk segment (child events) the plan must hold.
 Plan make_plan(int64_t n, int64_t H, int min_seg = 8);
 
+// The HIP error behind the last HULL_EHIP of this host thread.
+void note_hip_error(hipError_t e);
+
 #define HULL_LAUNCH_CHECK()                         \
   do {                                              \
     hipError_t e_ = hipGetLastError();              \
-    if (e_ != hipSuccess) return HULL_EHIP;         \
+    if (e_ != hipSuccess) {                         \
+      ::hull::note_hip_error(e_);                   \
+      return HULL_EHIP;                             \
+    }                                               \
   } while (0)
+
+// Entry of every call that launches: an error left pending by earlier,
+// unrelated HIP calls of this thread is cleared, so that the launch checks
+// see the call's own launches only.
+inline void clear_stale_hip_error() { (void)hipGetLastError(); }
 
 // Clear the device status words (a kernel, so that the call can be captured).
 void init_header(Header* h, hipStream_t s);

@@ -886,6 +886,16 @@ int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes) {
   return HULL_OK;
 }
 
+int32_t hull_schedule_defaults(hull_schedule_t* out) {
+  if (!out) return HULL_EINVAL;
+  const hull::Opts o = hull::resolve(nullptr);
+  out->serial_levels = o.serial_max;
+  out->walk_segment = o.seg;
+  out->fused_levels = o.fused;
+  out->reserved = 0;
+  return HULL_OK;
+}
+
 int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* bytes) {
   if (!bytes || total_points < 0 || total_points > hull::kMaxTotal || H < 1) return HULL_EINVAL;
   *bytes = hull::make_plan(total_points, H, 8).total;
@@ -894,12 +904,14 @@ int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* by
 
 int32_t hull_lower(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
                    void* d_ws, size_t ws_bytes, void* stream) {
+  hull::clear_stale_hip_error();
   return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
                          false, nullptr, 0);
 }
 
 int32_t hull_full(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
                   void* d_ws, size_t ws_bytes, void* stream) {
+  hull::clear_stale_hip_error();
   return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
                          true, nullptr, 0);
 }
@@ -907,6 +919,7 @@ int32_t hull_full(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap
 int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
                         int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream,
                         void* const* events, int32_t nevents) {
+  hull::clear_stale_hip_error();
   if (!events) return HULL_EINVAL;
   return hull::hull_runs(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, (hipStream_t)stream, true,
                          true, events, nevents);
@@ -916,6 +929,7 @@ int32_t hull_full_batched(const int32_t* d_xyz, const int64_t* d_offsets, const 
                           int64_t H, int32_t* d_faces, int64_t cap, int64_t* d_face_offsets,
                           int64_t* d_info, void* d_ws, size_t ws_bytes,
                           const hull_schedule_t* schedule, void* stream) {
+  hull::clear_stale_hip_error();
   return hull::batched(d_xyz, d_offsets, h_offsets, H, d_faces, cap, d_face_offsets, d_info, d_ws,
                        ws_bytes, schedule, (hipStream_t)stream);
 }
@@ -923,6 +937,7 @@ int32_t hull_full_batched(const int32_t* d_xyz, const int64_t* d_offsets, const 
 int32_t hull_movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,
                     int32_t* d_block_len, int32_t* d_order, int64_t* d_info, void* d_ws,
                     size_t ws_bytes, void* stream) {
+  hull::clear_stale_hip_error();
   return hull::movies(d_xyz, n, run, level, d_ev, d_block_len, d_order, d_info, d_ws, ws_bytes,
                       (hipStream_t)stream);
 }

@@ -5,6 +5,10 @@
 
 namespace hull {
 
+static thread_local int32_t g_last_hip_error = 0;
+
+void note_hip_error(hipError_t e) { g_last_hip_error = (int32_t)e; }
+
 static int64_t scan_partials_needed(int64_t len) { return (len + kScanBlock - 1) / kScanBlock; }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -94,3 +98,5 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
 }
 
 }  // namespace hull
+
+extern "C" int32_t hull_last_hip_error(void) { return hull::g_last_hip_error; }

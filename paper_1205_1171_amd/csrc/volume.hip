@@ -137,9 +137,11 @@ int32_t hull_volume_area_fwd(const float* d_p, const int64_t* d_pt_off, const in
   if (H < 0 || (H > 0 && (!d_p || !d_pt_off || !d_faces || !d_face_off || !d_V || !d_A)))
     return HULL_EINVAL;
   if (H == 0) return HULL_OK;
+  hull::clear_stale_hip_error();
   hipLaunchKernelGGL(hull::k_vol_area_fwd, dim3(H), dim3(hull::kVolThreads), 0,
                      (hipStream_t)stream, d_p, d_pt_off, d_faces, d_face_off, d_V, d_A);
-  return hipGetLastError() == hipSuccess ? HULL_OK : HULL_EHIP;
+  HULL_LAUNCH_CHECK();
+  return HULL_OK;
 }
 
 int32_t hull_volume_area_bwd(const float* d_p, const int64_t* d_pt_off, const int32_t* d_faces,
@@ -148,11 +150,13 @@ int32_t hull_volume_area_bwd(const float* d_p, const int64_t* d_pt_off, const in
   if (H < 0 || (H > 0 && (!d_p || !d_pt_off || !d_faces || !d_face_off || !d_grad_p)))
     return HULL_EINVAL;
   if (H == 0) return HULL_OK;
+  hull::clear_stale_hip_error();
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(hull::k_vol_area_zero, dim3(1024), dim3(256), 0, s, d_grad_p, d_pt_off, H);
   hipLaunchKernelGGL(hull::k_vol_area_bwd, dim3(16, H), dim3(256), 0, s, d_p, d_pt_off, d_faces,
                      d_face_off, d_gV, d_gA, d_grad_p);
-  return hipGetLastError() == hipSuccess ? HULL_OK : HULL_EHIP;
+  HULL_LAUNCH_CHECK();
+  return HULL_OK;
 }
 
 }  // extern "C"

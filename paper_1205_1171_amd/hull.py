@@ -32,6 +32,8 @@ class Schedule(ctypes.Structure):
 class HullError(RuntimeError):
     def __init__(self, code, where=""):
         msg = _strerror(code) if _lib is not None else str(code)
+        if code == HULL_EHIP and _lib is not None:
+            msg += f", hipError_t {_lib.hull_last_hip_error()}"
         super().__init__(f"{where}: {msg} ({code})")
         self.code = code
 
@@ -47,6 +49,10 @@ def lib():
         return _lib
     if not os.path.exists(SO):
         raise RuntimeError(f"HIP library not built: {SO} (run __graft_entry__.build())")
+    # torch first: its HIP runtime (libamdhip64.so.7) is then the one the
+    # library binds to.  Loaded the other way round, the process would hold
+    # two HIP runtimes and the library's would find no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(SO)
     P = ctypes.c_void_p
     i64 = ctypes.c_int64
@@ -54,6 +60,8 @@ def lib():
     sz = ctypes.c_size_t
     L.hull_strerror.argtypes = [i32]
     L.hull_strerror.restype = ctypes.c_char_p
+    L.hull_last_hip_error.argtypes = []
+    L.hull_last_hip_error.restype = i32
     L.hull_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(sz)]
     L.hull_workspace_bytes.restype = i32
     for f in (L.hull_lower, L.hull_full):
@@ -65,6 +73,8 @@ def lib():
     L.hull_workspace_bytes_batched.restype = i32
     L.hull_full_batched.argtypes = [P, P, P, i64, P, i64, P, P, P, sz, ctypes.POINTER(Schedule), P]
     L.hull_full_batched.restype = i32
+    L.hull_schedule_defaults.argtypes = [ctypes.POINTER(Schedule)]
+    L.hull_schedule_defaults.restype = i32
     L.hull_movies.argtypes = [P, i64, i32, i32, P, P, P, P, P, sz, P]
     L.hull_movies.restype = i32
     L.hull_volume_area_fwd.argtypes = [P, P, P, P, i32, P, P, P]
@@ -78,8 +88,9 @@ def lib():
 def exported_symbols():
     """Names declared in include/hull3d.h that the library exports."""
     L = lib()
-    names = ["hull_strerror", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
-             "hull_workspace_bytes_batched", "hull_full_batched", "hull_movies",
+    names = ["hull_strerror", "hull_last_hip_error", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
+             "hull_workspace_bytes_batched", "hull_full_batched", "hull_schedule_defaults",
+             "hull_movies",
              "hull_volume_area_fwd", "hull_volume_area_bwd"]
     return [n for n in names if hasattr(L, n)]
 
@@ -90,6 +101,15 @@ def workspace_bytes(n, flags=0):
     if rc:
         raise HullError(rc, "hull_workspace_bytes")
     return out.value
+
+
+def schedule_defaults():
+    """The schedule the library uses for calls that pass none."""
+    out = Schedule()
+    rc = lib().hull_schedule_defaults(ctypes.byref(out))
+    if rc:
+        raise HullError(rc, "hull_schedule_defaults")
+    return out
 
 
 def workspace_bytes_batched(total_points, H):
@@ -256,3 +276,67 @@ def volume_area_bwd(p, pt_off, faces, face_off, gV, gA, stream=None):
     if rc:
         raise HullError(rc, "hull_volume_area_bwd")
     return g
+
+
+class BatchedHull:
+    """A fixed batch layout with its device buffers, for repeated calls of
+    hull_full_batched on inputs of that layout (same offsets, same input
+    buffer).  ``run`` launches on the current stream; ``capture`` records one
+    call into a HIP graph (the library makes no allocation, copy, memset or
+    host synchronisation, so the whole call is capturable) and ``replay``
+    launches it."""
+
+    def __init__(self, xyz, offsets, schedule=None):
+        import torch
+        _check_points(xyz)
+        self.xyz = xyz
+        self.h_off = torch.as_tensor(offsets, dtype=torch.int64).cpu().contiguous()
+        self.H = self.h_off.numel() - 1
+        if self.H < 1 or int(self.h_off[-1]) != xyz.shape[0]:
+            raise ValueError("offsets must have H + 1 >= 2 entries ending at the point count")
+        dev = xyz.device
+        n = xyz.shape[0]
+        self.d_off = self.h_off.to(dev)
+        self.cap = max(2 * n, 1)
+        self.faces = torch.empty((self.cap, 3), dtype=torch.int32, device=dev)
+        self.face_off = torch.zeros(self.H + 1, dtype=torch.int64, device=dev)
+        self.info = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.ws = torch.empty(max(workspace_bytes_batched(n, self.H), 256), dtype=torch.uint8,
+                              device=dev)
+        self.schedule = schedule
+        self.graph = None
+
+    def run(self, stream=None):
+        sc = ctypes.byref(self.schedule) if self.schedule is not None else None
+        rc = lib().hull_full_batched(
+            ctypes.c_void_p(self.xyz.data_ptr()), ctypes.c_void_p(self.d_off.data_ptr()),
+            ctypes.c_void_p(self.h_off.data_ptr()), self.H, ctypes.c_void_p(self.faces.data_ptr()),
+            self.cap, ctypes.c_void_p(self.face_off.data_ptr()), ctypes.c_void_p(self.info.data_ptr()),
+            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), sc, _stream(stream))
+        if rc:
+            raise HullError(rc, "hull_full_batched")
+
+    def capture(self):
+        import torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()  # warm-up outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def result(self):
+        """Checked (faces [F, 3], face_offsets [H + 1]) after a call (blocking)."""
+        st, F = (int(v) for v in self.info.cpu())
+        if st:
+            raise HullError(st, "device")
+        return self.faces[:F], self.face_off

@@ -150,9 +150,12 @@ def test_cfg4_full_digest(H, ws):
     rec = json.load(open(path))
     pts, off, _ = workloads.cfg4()
     assert hashlib.sha256(np.ascontiguousarray(pts, dtype="<i4").tobytes()).hexdigest() == rec["input_sha256"]
-    say("cfg4 full", len(off) - 1, int(off[-1]))
+    from paper_1205_1171_amd import autotune
+    sched = autotune.lookup(off)  # the schedule the benchmark uses (None = defaults)
+    say("cfg4 full", len(off) - 1, int(off[-1]), "schedule",
+        None if sched is None else (sched.serial_levels, sched.walk_segment))
     x = torch.from_numpy(pts).cuda()
-    f, fo = H.hull_batched_sync(x, off, ws=ws)
+    f, fo = H.hull_batched_sync(x, off, schedule=sched, ws=ws)
     f, fo = f.cpu().numpy(), fo.cpu().numpy()
     counts = np.diff(fo)
     assert counts.tolist() == rec["F_per_cloud"]
@@ -160,3 +163,54 @@ def test_cfg4_full_digest(H, ws):
     for h in range(len(off) - 1):
         sha.update(validate.canonical(f[fo[h]:fo[h + 1]]).astype("<i4").tobytes())
     assert sha.hexdigest() == rec["sha256_full"]
+
+
+def test_graph_replays_match_eager(H, ws):
+    """The batched call captured in a HIP graph: every replay, with eager
+    work and synchronisations between them, gives the eager call's faces."""
+    import torch
+    rng = np.random.default_rng(21)
+    clouds = ragged_batch(rng, 60)
+    off = np.zeros(len(clouds) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(c) for c in clouds])
+    x = torch.from_numpy(np.ascontiguousarray(np.concatenate(clouds))).cuda()
+    bh = H.BatchedHull(x, off)
+    bh.run()
+    f0, fo0 = (t.clone() for t in bh.result())
+    say("graph capture")
+    bh.capture()
+    for rep in range(4):
+        bh.faces.fill_(-7)
+        bh.face_off.fill_(-7)
+        bh.info.fill_(-7)
+        torch.cuda.synchronize()
+        bh.replay()
+        f, fo = bh.result()
+        say("replay", rep, int(fo[-1]))
+        assert torch.equal(fo, fo0) and torch.equal(f, f0), rep
+        y = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        del y
+    for h, c in enumerate(clouds):
+        got = f0[fo0[h]:fo0[h + 1]].cpu().numpy()
+        assert same(got, oracle_faces(c)), h
+
+
+def test_autotuner_schedules_agree(H, ws):
+    """Every schedule the tuner tries gives the same faces; the chosen one
+    is from its grid."""
+    import torch
+    from paper_1205_1171_amd import autotune
+    pts, off, _ = workloads.cfg4(H=120, lo=3.0, hi=13.0)
+    x = torch.from_numpy(pts).cuda()
+    best, times = autotune.tune(x, off, reps=1, serial_levels=(6, 9, 99), walk_segments=(8, 32),
+                                save=False, log=say)
+    assert (best.serial_levels, best.walk_segment) in times
+    ref = None
+    for sl, seg in times:
+        f, fo = H.hull_batched_sync(x, off, schedule=H.Schedule(sl, seg, 0), ws=ws)
+        cur = [validate.canonical(f[fo[h]:fo[h + 1]].cpu().numpy()) for h in range(len(off) - 1)]
+        if ref is None:
+            ref = cur
+        else:
+            assert all(a.shape == b.shape and (a == b).all() for a, b in zip(ref, cur)), (sl, seg)
