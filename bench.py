@@ -25,7 +25,7 @@ Also reported on the same line:
                   the n = 2^24 workload.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
-                       [--no-batched] [--no-diff] [--no-cpu]
+                       [--no-batched] [--no-diff] [--no-per-hull] [--no-cpu]
 """
 import argparse
 import ctypes
@@ -250,7 +250,7 @@ def single(args, hull, workloads):
     return out, p
 
 
-def batched(hull, workloads, autotune, reps):
+def batched(hull, workloads, autotune, reps, per_hull=True):
     """cfg4: one graph-captured batched call against one call per cloud."""
     import numpy as np
     import torch
@@ -292,7 +292,7 @@ def batched(hull, workloads, autotune, reps):
     sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     base = x.data_ptr()
 
-    def per_hull(count):
+    def run_per_hull(count):
         for h in range(count):
             rc = L_.hull_full(ctypes.c_void_p(base + 12 * int(off[h])), int(sizes[h]),
                               ctypes.c_void_p(fbuf.data_ptr()), fbuf.shape[0],
@@ -301,9 +301,11 @@ def batched(hull, workloads, autotune, reps):
             if rc:
                 raise hull.HullError(rc, "hull_full")
 
-    per_hull(min(H, 200))  # warm-up
-    ms_loop = timed(lambda: per_hull(H), 1)
-    log(f"one launch per cloud: {ms_loop:.1f} ms")
+    ms_loop = None
+    if per_hull:
+        run_per_hull(min(H, 200))  # warm-up
+        ms_loop = timed(lambda: run_per_hull(H), 1)
+        log(f"one launch per cloud: {ms_loop:.1f} ms")
     s = sched if sched is not None else hull.schedule_defaults()
     return {
         "workload": f"cfg4: {H} clouds, sizes floor(2^U), U ~ U[3,16], 50/50 ball/sphere of "
@@ -312,11 +314,11 @@ def batched(hull, workloads, autotune, reps):
         "schedule": {"serial_levels": s.serial_levels, "walk_segment": s.walk_segment,
                      "source": "autotuner cache" if sched is not None else "library defaults"},
         "ms_graph": round(ms_graph, 3), "ms_eager": round(ms_eager, 3),
-        "ms_one_launch_per_hull": round(ms_loop, 3),
+        "ms_one_launch_per_hull": round(ms_loop, 3) if ms_loop else None,
         "hulls_per_s": round(H / (ms_graph / 1e3), 1),
         "hulls_per_s_eager": round(H / (ms_eager / 1e3), 1),
-        "hulls_per_s_one_launch_per_hull": round(H / (ms_loop / 1e3), 1),
-        "speedup_vs_one_launch_per_hull": round(ms_loop / ms_graph, 2),
+        "hulls_per_s_one_launch_per_hull": round(H / (ms_loop / 1e3), 1) if ms_loop else None,
+        "speedup_vs_one_launch_per_hull": round(ms_loop / ms_graph, 2) if ms_loop else None,
         "Mpoints_per_s": round(N / (ms_graph / 1e3) / 1e6, 2),
         "bit_exact": bit_exact,
     }
@@ -421,6 +423,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-per-hull", action="store_true",
+                    help="skip the one-launch-per-cloud comparison (for short profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the hull is not "
@@ -431,7 +435,8 @@ def main():
     hull.lib()
     out, p = single(args, hull, workloads)
     if not args.no_batched:
-        out["batched"] = batched(hull, workloads, autotune, reps=3)
+        out["batched"] = batched(hull, workloads, autotune, reps=3,
+                                 per_hull=not args.no_per_hull)
     if not args.no_diff:
         out["differentiation"] = differentiation(hull, workloads, autotune, reps=5)
     if not args.no_cpu:

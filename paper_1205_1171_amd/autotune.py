@@ -38,8 +38,12 @@ def shape_key(offsets):
 
 
 def device_key():
+    """Architecture and compute-unit count, e.g. gfx950_256CU."""
     import torch
-    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    if not torch.cuda.is_available():
+        return "cpu"
+    pr = torch.cuda.get_device_properties(0)
+    return f"{pr.gcnArchName.split(':')[0]}_{pr.multi_processor_count}CU"
 
 
 def _load():

@@ -50,6 +50,7 @@ struct Plan {
   size_t ecnt[2], eoff[2], cslot[2], cmerge[2];
   size_t segS[2], segBase[2], segMerge[2], segCnt[2], segOff[2];
   size_t bev[2], btau[2], buv[2], nB[2], boff[2], uv0[2], surv[2], jb[2], pre[2];
+  size_t aR[2], aL[2], aT[2], wf[2];
   // face counts of the hulls of a batch
   size_t fcnt;
   size_t total;

@@ -88,7 +88,7 @@ __device__ __forceinline__ Lead lead_of(int4 P, int4 Q, int4 R, int zs) {
 // points with equal x (all triples on such a pair share a standard part),
 // with no 256-bit arithmetic; only when all three vanish (or D0 = D1 = 0)
 // does the full cascade run.
-__device__ __noinline__ int tri_cmp_mid(const int4* pts, Tri A, Tri B, int zs) {
+__device__ __forceinline__ int tri_cmp_mid_body(const int4* pts, Tri A, Tri B, int zs) {
   Lead a = lead_of(pts[A.a], pts[A.w], pts[A.b], zs);
   Lead b = lead_of(pts[B.a], pts[B.w], pts[B.b], zs);
   int sa = a.d0 ? (a.d0 > 0 ? 1 : -1) : (a.d1 > 0) - (a.d1 < 0);
@@ -104,11 +104,21 @@ __device__ __noinline__ int tri_cmp_mid(const int4* pts, Tri A, Tri B, int zs) {
   return tri_cmp_exact(pts, A, B, zs);
 }
 
+// The mid tier as a call (kernels with many live registers) ...
+__device__ __noinline__ int tri_cmp_mid(const int4* pts, Tri A, Tri B, int zs) {
+  return tri_cmp_mid_body(pts, A, B, zs);
+}
+
+// Order of two events: 0 for the same triple, else the standard-part filter,
+// then the mid tier (inlined with kInlineMid: the lane-serial merge, where
+// exact standard-part ties are frequent and a call costs more than the
+// registers).
+template <bool kInlineMid = false>
 __device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand& B, int zs) {
   if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
   int s = std_cmp(A.st, B.st);
   if (s) return s;
-  return tri_cmp_mid(pts, A.t, B.t, zs);
+  return kInlineMid ? tri_cmp_mid_body(pts, A.t, B.t, zs) : tri_cmp_mid(pts, A.t, B.t, zs);
 }
 
 // Perturbed sign of D when D0 = D1 = 0 (cold path).
@@ -184,8 +194,8 @@ struct ParRun {
   double* entRt;  // their times
   Event* entL;
   double* entLt;
-  int* ctr;       // [0] R entries, [1] L entries, [2] touched lists; [4..7] level totals:
-                  // merges, child events, walk segments, bridge events
+  int* ctr;       // [2] touched lists; [4..7] level totals: merges, child events,
+                  // walk segments, bridge events
   int* touched;   // (point << 1 | side) of every allocated list
   int* ecnt;      // per merge: child events (mcap + 1)
   int* eoff;      // exclusive scan of ecnt
@@ -205,6 +215,10 @@ struct ParRun {
   int* surv;      // per child event: survives into the merged movie (+1 entry)
   int* jb;        // per child event: # bridge events before it
   int* pre;       // exclusive scan of surv
+  int* aR;        // per child event: list entries (R side) of the lists it allocates,
+  int* aL;        //   then their start (exclusive scan); L side
+  int* aT;        //   touched lists it allocates, then their start
+  unsigned char* wf;  // per child event: which of its lists it allocates (bits R a, R w, L b, L w)
   int zs;
 };
 

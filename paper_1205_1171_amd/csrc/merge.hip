@@ -104,6 +104,17 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   double st2 = 0.0, st3 = 0.0, st4 = 0.0, st5 = 0.0;
   bool ok2 = false, ok3 = false, ok4 = false, ok5 = false;
   unsigned dirty = 0xF;
+  // the next event of each child, loaded one iteration ahead
+  Event EL{0, 0, 0, 0}, ER{0, 0, 0, 0};
+  double tL = 0.0, tR = 0.0;
+  if (nL > 0) {
+    EL = Lev[0];
+    tL = Ltau[0];
+  }
+  if (nR > 0) {
+    ER = Rev[0];
+    tR = Rtau[0];
+  }
   const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
   for (int64_t it = 0;; ++it) {
     if (it > iter_cap) {
@@ -167,39 +178,37 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       else if (bbi == 4) { ba = u; bw = pvv; bb = v; bk = 1; }
       else { ba = u; bw = v; bb = nv; bk = 0; }
     }
-#define HULL_CHILD(IDX, EV, TAU, Q)                                        \
+#define HULL_CHILD(IDX, E_, T_)                                            \
   {                                                                      \
-    const Event E_ = (EV)[Q];                                            \
-    const double t_ = (TAU)[Q];                                          \
     bool take_ = bi < 0;                                                 \
     if (!take_) {                                                        \
       Cand x_, y_;                                                       \
-      x_.t = Tri{E_.a, E_.w, E_.b};                                      \
-      x_.st = t_;                                                        \
-      x_.kind = E_.kind;                                                 \
+      x_.t = Tri{(E_).a, (E_).w, (E_).b};                                \
+      x_.st = (T_);                                                      \
+      x_.kind = 0;                                                       \
       y_.t = Tri{ba, bw, bb};                                            \
       y_.st = bs;                                                        \
-      y_.kind = bk;                                                      \
-      take_ = ev_cmp(pts, x_, y_, zs) < 0;                               \
+      y_.kind = 0;                                                       \
+      take_ = ev_cmp(pts, x_, y_, zs) < 0;                         \
     }                                                                    \
     if (take_) {                                                         \
       bi = (IDX);                                                        \
-      ba = E_.a;                                                         \
-      bw = E_.w;                                                         \
-      bb = E_.b;                                                         \
-      bs = t_;                                                           \
+      ba = (E_).a;                                                       \
+      bw = (E_).w;                                                       \
+      bb = (E_).b;                                                       \
+      bs = (T_);                                                         \
     }                                                                    \
   }
-    if (i < nL) HULL_CHILD(0, Lev, Ltau, i)
-    if (j < nR) HULL_CHILD(1, Rev, Rtau, j)
+    if (i < nL) HULL_CHILD(0, EL, tL)
+    if (j < nR) HULL_CHILD(1, ER, tR)
 #undef HULL_CHILD
     if (bi < 0) break;
     // the kind of the chosen event, from its source once the choice is made
     // (not carried through the selection: hipcc for gfx950 has dropped the
     // condition on such a carried field, taking the old value for lanes that
     // switch candidates)
-    if (bi == 0) bk = Lev[i].kind;
-    else if (bi == 1) bk = Rev[j].kind;
+    if (bi == 0) bk = EL.kind;
+    else if (bi == 1) bk = ER.kind;
     else bk = (bi == 2 || bi == 4) ? 1 : 0;
     T.t = Tri{ba, bw, bb};
     T.st = bs;
@@ -207,7 +216,22 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     haveT = true;
     bool emit = false;
     if (bi <= 1) {
+      // the child's next event, issued now so that its latency overlaps the
+      // rest of this iteration
+      if (bi == 0) {
+        if (++i < nL) {
+          EL = Lev[i];
+          tL = Ltau[i];
+        }
+      } else {
+        if (++j < nR) {
+          ER = Rev[j];
+          tR = Rtau[j];
+        }
+      }
       emit = bi == 0 ? (bw < u) : (bw > v);
+      // the event sets nx(a) and pv(b) (and, inserting w, both links of w)
+      const int na = bk ? bw : bb, pb = bk ? bw : ba;
       if (bk) {  // insertion into the child's chain
         nx[ba] = bw;
         pv[bb] = bw;
@@ -217,25 +241,26 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
         nx[ba] = bb;
         pv[bb] = ba;
       }
-      if (bi == 0) ++i; else ++j;
-      // a link of u or v may have changed
-      const int nu2 = nx[u], pu2 = pv[u], pv2 = pv[v], nv2 = nx[v];
-      dirty = (nu2 != nu ? 1u : 0u) | (pu2 != pu ? 2u : 0u) | (pv2 != pvv ? 4u : 0u) |
-              (nv2 != nv ? 8u : 0u);
-      nu = nu2;
-      pu = pu2;
-      pvv = pv2;
-      nv = nv2;
+      // links of u and v it changed (w is never u or v when inserted)
+      unsigned d = 0;
+      if (ba == u) { nu = na; d |= 1u; }
+      if (bb == u) { pu = pb; d |= 2u; }
+      if (bb == v) { pvv = pb; d |= 4u; }
+      if (ba == v) { nv = na; d |= 8u; }
+      dirty = d;
     } else {
       emit = true;
-      if (bi == 2) { u = nu; Pu = pts[u]; }
-      else if (bi == 3) { u = pu; Pu = pts[u]; }
-      else if (bi == 4) { v = pvv; Pv = pts[v]; }
-      else { v = nv; Pv = pts[v]; }
-      nu = nx[u];
-      pu = pv[u];
-      pvv = pv[v];
-      nv = nx[v];
+      if (bi == 2 || bi == 3) {
+        u = bi == 2 ? nu : pu;
+        Pu = pts[u];
+        nu = nx[u];
+        pu = pv[u];
+      } else {
+        v = bi == 4 ? pvv : nv;
+        Pv = pts[v];
+        pvv = pv[v];
+        nv = nx[v];
+      }
       dirty = 0xF;
     }
     if (emit) {
@@ -646,6 +671,10 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.surv = (int*)(ws + pl.surv[r]);
     Q.jb = (int*)(ws + pl.jb[r]);
     Q.pre = (int*)(ws + pl.pre[r]);
+    Q.aR = (int*)(ws + pl.aR[r]);
+    Q.aL = (int*)(ws + pl.aL[r]);
+    Q.aT = (int*)(ws + pl.aT[r]);
+    Q.wf = (unsigned char*)(ws + pl.wf[r]);
     if (on)
       hipLaunchKernelGGL(k_init_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0,
                          (int*)(ws + pl.len[r][0]), Q.claimR, Q.claimL, n);

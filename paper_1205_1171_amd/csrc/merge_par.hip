@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(256) k_par_prep(ParLevel P) {
   const int64_t half = int64_t(1) << (P.k - 1);
   GRID_STRIDE(g, (int64_t)merges + 1) {
     if (g == 0) {
-      R.ctr[0] = R.ctr[1] = R.ctr[2] = 0;
+      R.ctr[2] = 0;
       R.ctr[4] = merges;
     }
     if (g < merges && !P.h->err) {
@@ -364,78 +364,85 @@ __global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
   }
 }
 
-// Inclusive prefix sum over the 64 lanes of a wavefront (every lane takes
-// part).
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-// One list per touched (point, side), allocated by whichever event claims it
-// first at this level (claim stamp = the level).  The list space is handed
-// out per wavefront: one atomic per wavefront and counter, each claim's
-// offset from the wavefront's prefix sums.
-__global__ void __launch_bounds__(256) k_par_alloc(ParLevel P) {
+// One list per touched (point, side), allocated by whichever child event
+// claims it first at this level (claim stamp = the level).  Pass 1: each
+// event claims, and records how many list entries and lists it allocates;
+// after exclusive scans of those counts, pass 2 places the lists.  (No
+// shared counters: space comes from prefix sums.)
+__global__ void __launch_bounds__(256) k_par_claim(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
   const int E = R.ctr[5], st = R.stamp;
-  const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  GRID_STRIDE(c, (int64_t)E + 1) {
+    if (c == E) {  // the scans read one entry past the last event
+      R.aR[c] = R.aL[c] = R.aT[c] = 0;
+      continue;
+    }
+    const Event X = R.ev_in[R.cslot[c]];
+    unsigned bits = 0;
+    int nR = 0, nL = 0;
+    if (atomicExch(&R.claimR[X.a], st) != st) {
+      bits |= 1u;
+      nR += R.cntR[X.a];
+    }
+    if (atomicExch(&R.claimL[X.b], st) != st) {
+      bits |= 4u;
+      nL += R.cntL[X.b];
+    }
+    if (X.kind) {
+      if (atomicExch(&R.claimR[X.w], st) != st) {
+        bits |= 2u;
+        nR += R.cntR[X.w];
+      }
+      if (atomicExch(&R.claimL[X.w], st) != st) {
+        bits |= 8u;
+        nL += R.cntL[X.w];
+      }
+    }
+    R.aR[c] = nR;
+    R.aL[c] = nL;
+    R.aT[c] = __builtin_popcount(bits);
+    R.wf[c] = (unsigned char)bits;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
+  const ParRun& R = P.run[blockIdx.y];
+  if (!R.pts) return;
+  const int E = R.ctr[5];
   // capacities: 4n entries per side (at most 2 per child event, 2n events),
   // 2n touched lists (one per point and side)
   const int64_t ent_cap = 2 * (int64_t)P.ecap, touched_cap = P.ecap;
-  // the loop bound is the same for the 64 lanes of a wavefront
-  for (int64_t w0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); w0 < E; w0 += stride) {
-    const int64_t c = w0 + lane;
-    int pR0 = kNil, pR1 = kNil, pL0 = kNil, pL1 = kNil;
-    if (c < E) {
-      const Event X = R.ev_in[R.cslot[c]];
-      if (atomicExch(&R.claimR[X.a], st) != st) pR0 = X.a;
-      if (atomicExch(&R.claimL[X.b], st) != st) pL0 = X.b;
-      if (X.kind) {
-        if (atomicExch(&R.claimR[X.w], st) != st) pR1 = X.w;
-        if (atomicExch(&R.claimL[X.w], st) != st) pL1 = X.w;
-      }
-    }
-    const int cR0 = pR0 != kNil ? R.cntR[pR0] : 0, cR1 = pR1 != kNil ? R.cntR[pR1] : 0;
-    const int cL0 = pL0 != kNil ? R.cntL[pL0] : 0, cL1 = pL1 != kNil ? R.cntL[pL1] : 0;
-    const int nT = (pR0 != kNil) + (pR1 != kNil) + (pL0 != kNil) + (pL1 != kNil);
-    const int iR = wave_incl_scan(cR0 + cR1), iL = wave_incl_scan(cL0 + cL1),
-              iT = wave_incl_scan(nT);
-    const int tR = __shfl(iR, 63, 64), tL = __shfl(iL, 63, 64), tT = __shfl(iT, 63, 64);
-    int bR = 0, bL = 0, bT = 0;
-    if (lane == 0) {
-      if (tR) bR = atomicAdd(&R.ctr[0], tR);
-      if (tL) bL = atomicAdd(&R.ctr[1], tL);
-      if (tT) bT = atomicAdd(&R.ctr[2], tT);
-    }
-    bR = __shfl(bR, 0, 64) + iR - (cR0 + cR1);
-    bL = __shfl(bL, 0, 64) + iL - (cL0 + cL1);
-    bT = __shfl(bT, 0, 64) + iT - nT;
-    if (bR + cR0 + cR1 > ent_cap || bL + cL0 + cL1 > ent_cap || bT + nT > touched_cap) {
-      atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+  if (R.aR[E] > ent_cap || R.aL[E] > ent_cap || R.aT[E] > touched_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+    return;
+  }
+  GRID_STRIDE(c, (int64_t)E + 1) {
+    if (c == E) {
+      R.ctr[2] = R.aT[E];  // touched lists of the level
       continue;
     }
-    if (pR0 != kNil) {
-      R.offR[pR0] = bR;
-      R.touched[bT++] = pR0 << 1;
+    const unsigned bits = R.wf[c];
+    if (!bits) continue;
+    const Event X = R.ev_in[R.cslot[c]];
+    int bR = R.aR[c], bL = R.aL[c], bT = R.aT[c];
+    if (bits & 1u) {
+      R.offR[X.a] = bR;
+      bR += R.cntR[X.a];
+      R.touched[bT++] = X.a << 1;
     }
-    if (pR1 != kNil) {
-      R.offR[pR1] = bR + cR0;
-      R.touched[bT++] = pR1 << 1;
+    if (bits & 2u) {
+      R.offR[X.w] = bR;
+      R.touched[bT++] = X.w << 1;
     }
-    if (pL0 != kNil) {
-      R.offL[pL0] = bL;
-      R.touched[bT++] = (pL0 << 1) | 1;
+    if (bits & 4u) {
+      R.offL[X.b] = bL;
+      bL += R.cntL[X.b];
+      R.touched[bT++] = (X.b << 1) | 1;
     }
-    if (pL1 != kNil) {
-      R.offL[pL1] = bL + cL0;
-      R.touched[bT++] = (pL1 << 1) | 1;
+    if (bits & 8u) {
+      R.offL[X.w] = bL;
+      R.touched[bT++] = (X.w << 1) | 1;
     }
   }
 }
@@ -627,7 +634,16 @@ int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_par_totals, dim3(1, 2), dim3(64), 0, s, P);
   hipLaunchKernelGGL(k_par_enum, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_count, g2, b256, 0, s, P);
-  hipLaunchKernelGGL(k_par_alloc, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_claim, g2, b256, 0, s, P);
+  for (int r = 0; r < 2; ++r) {
+    const ParRun& R = P.run[r];
+    if (!R.pts) continue;
+    int32_t rc = exclusive_scan_dev(R.aR, R.aR, R.ctr + 5, 1, P.ecap + 1, partials, s);
+    if (!rc) rc = exclusive_scan_dev(R.aL, R.aL, R.ctr + 5, 1, P.ecap + 1, partials, s);
+    if (!rc) rc = exclusive_scan_dev(R.aT, R.aT, R.ctr + 5, 1, P.ecap + 1, partials, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_par_place, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_fill, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_sort, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_segtable, g2, b256, 0, s, P);

@@ -92,6 +92,10 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.surv[r] = take((2 * nn + 1) * 4);
     p.jb[r] = take(2 * nn * 4);
     p.pre[r] = take((2 * nn + 1) * 4);
+    p.aR[r] = take((2 * nn + 1) * 4);
+    p.aL[r] = take((2 * nn + 1) * 4);
+    p.aT[r] = take((2 * nn + 1) * 4);
+    p.wf[r] = take(2 * nn);
   }
   p.total = off;
   return p;
