@@ -206,6 +206,7 @@ struct ParRun {
   int* segMerge;  // per segment: its merge
   int* segCnt;    // per segment: # bridge events
   int* segOff;    // exclusive scan of segCnt
+  int2* segUV;    // per segment: the bridge at its start (found by the counting pass)
   Event* bev;     // bridge events of merge (s, e) at slots [2s, 2s + nB)
   double* btau;
   int2* buv;      // (u, v) after each bridge event

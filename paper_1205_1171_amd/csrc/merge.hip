@@ -662,6 +662,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.segMerge = (int*)(ws + pl.segMerge[r]);
     Q.segCnt = (int*)(ws + pl.segCnt[r]);
     Q.segOff = (int*)(ws + pl.segOff[r]);
+    Q.segUV = (int2*)(ws + pl.segUV[r]);
     Q.bev = (Event*)(ws + pl.bev[r]);
     Q.btau = (double*)(ws + pl.btau[r]);
     Q.buv = (int2*)(ws + pl.buv[r]);

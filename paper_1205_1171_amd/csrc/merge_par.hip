@@ -112,6 +112,21 @@ __device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) 
   X.pv = X.cl > 0 ? left_after(R.entL[X.oL + X.cl - 1], p) : R.pv0[p];
 }
 
+// One link of p just after T (the right link with `right`), without the rest
+// of the endpoint state: the tangent search needs only that.
+__device__ int link_after(const ParRun& R, int p, bool right, bool haveT, const Cand& T) {
+  if (right) {
+    if (R.claimR[p] != R.stamp) return R.nx0[p];
+    const int o = R.offR[p];
+    const int c = first_after(R, R.entR, R.entRt, o, R.cntR[p], haveT, T);
+    return c > 0 ? right_after(R.entR[o + c - 1], p) : R.nx0[p];
+  }
+  if (R.claimL[p] != R.stamp) return R.pv0[p];
+  const int o = R.offL[p];
+  const int c = first_after(R, R.entL, R.entLt, o, R.cntL[p], haveT, T);
+  return c > 0 ? left_after(R.entL[o + c - 1], p) : R.pv0[p];
+}
+
 // Orientation of the rank-ordered triple (a, b, c) just after event T: its
 // sign at t = -inf is sign(D), and it flips once, at its own event.
 __device__ int orient_after(const int4* pts, int a, int b, int c, const Cand& T, int zs) {
@@ -144,7 +159,7 @@ __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
 // bridge in `uv0`.
 __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e, int seg,
                             int S, Event* out, double* out_tau, int2* out_uv, int cap,
-                            int2* uv0) {
+                            int2* uv0, int2* start_uv, bool have_start) {
   const int4* pts = R.pts;
   const int zs = R.zs;
   bool haveT = false, haveEnd = false;
@@ -162,35 +177,46 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
     haveEnd = true;
   }
   // the bridge at the start of the segment: walk to the lower common tangent
-  // of the two chains, from the inner ends of the blocks
-  Endpoint U{(int)m - 1, 0, 0, 0, 0, 0, 0, 0, 0}, V{(int)m, 0, 0, 0, 0, 0, 0, 0, 0};
-  lookup(R, U, haveT, T);
-  lookup(R, V, haveT, T);
-  for (int guard = 0;; ++guard) {
-    if (guard > 2 * (e - s) + 4) {
+  // of the two chains, from the inner ends of the blocks (each step needs one
+  // link of one endpoint); the counting pass leaves it for the writing pass
+  int up = (int)m - 1, vp = (int)m;
+  if (have_start) {
+    up = start_uv->x;
+    vp = start_uv->y;
+    if (up < s || up >= m || vp < m || vp >= e) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
       return 0;
     }
-    if (V.nx != kNil) {
-      int o = haveT ? orient_after(pts, U.p, V.p, V.nx, T, zs)
-                    : d_sign(pts[U.p], pts[V.p], pts[V.nx]);
-      if (o < 0) {
-        V.p = V.nx;
-        lookup(R, V, haveT, T);
-        continue;
+  } else {
+    int vnx = link_after(R, vp, true, haveT, T), upv = link_after(R, up, false, haveT, T);
+    for (int guard = 0;; ++guard) {
+      if (guard > 2 * (e - s) + 4) {
+        atomicCAS(&h->err, 0, HULL_EINTERNAL);
+        return 0;
       }
-    }
-    if (U.pv != kNil) {
-      int o = haveT ? orient_after(pts, U.pv, U.p, V.p, T, zs)
-                    : d_sign(pts[U.pv], pts[U.p], pts[V.p]);
-      if (o < 0) {
-        U.p = U.pv;
-        lookup(R, U, haveT, T);
-        continue;
+      if (vnx != kNil) {
+        int o = haveT ? orient_after(pts, up, vp, vnx, T, zs) : d_sign(pts[up], pts[vp], pts[vnx]);
+        if (o < 0) {
+          vp = vnx;
+          vnx = link_after(R, vp, true, haveT, T);
+          continue;
+        }
       }
+      if (upv != kNil) {
+        int o = haveT ? orient_after(pts, upv, up, vp, T, zs) : d_sign(pts[upv], pts[up], pts[vp]);
+        if (o < 0) {
+          up = upv;
+          upv = link_after(R, up, false, haveT, T);
+          continue;
+        }
+      }
+      break;
     }
-    break;
+    if (start_uv) *start_uv = make_int2(up, vp);
   }
+  Endpoint U{up, 0, 0, 0, 0, 0, 0, 0, 0}, V{vp, 0, 0, 0, 0, 0, 0, 0, 0};
+  lookup(R, U, haveT, T);
+  lookup(R, V, haveT, T);
   if (uv0) *uv0 = make_int2(U.p, V.p);
   int4 Pu = pts[U.p], Pv = pts[V.p];
   int nb = 0;
@@ -516,13 +542,14 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
       continue;
     }
     if (!write) {
-      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, nullptr, 0, nullptr);
+      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, nullptr, 0, nullptr,
+                                 &R.segUV[t], false);
       continue;
     }
     const int64_t off = R.segOff[t] - R.segOff[first];
     const int cap = (int)(2 * (e - s) - off);
     walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.btau + 2 * s + off,
-                 R.buv + 2 * s + off, cap, i == 0 ? &R.uv0[g] : nullptr);
+                 R.buv + 2 * s + off, cap, i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], true);
     if (i == 0) R.nB[g] = R.segOff[first + S] - R.segOff[first];
   }
 }

@@ -83,6 +83,7 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.segMerge[r] = take((p.seg_cap + 1) * 4);
     p.segCnt[r] = take((p.seg_cap + 1) * 4);
     p.segOff[r] = take((p.seg_cap + 1) * 4);
+    p.segUV[r] = take((p.seg_cap + 1) * sizeof(int2));
     p.bev[r] = take(2 * nn * sizeof(Event));
     p.btau[r] = take(2 * nn * sizeof(double));
     p.buv[r] = take(2 * nn * sizeof(int2));
