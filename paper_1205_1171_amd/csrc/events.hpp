@@ -69,15 +69,15 @@ struct Lead {
 };
 
 __device__ __forceinline__ Lead lead_of(int4 P, int4 Q, int4 R, int zs) {
-  int64_t dx1 = (int64_t)Q.x - P.x, dx2 = (int64_t)R.x - P.x;
-  int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
-  int64_t dz1 = (int64_t)Q.z - P.z, dz2 = (int64_t)R.z - P.z;
-  int64_t di1 = (int64_t)Q.w - P.w, di2 = (int64_t)R.w - P.w;
+  const int dx1 = dif32(Q.x, P.x), dx2 = dif32(R.x, P.x);
+  const int dy1 = dif32(Q.y, P.y), dy2 = dif32(R.y, P.y);
+  const int dz1 = dif32(Q.z, P.z), dz2 = dif32(R.z, P.z);
+  const int di1 = Q.w - P.w, di2 = R.w - P.w;
   Lead L;
-  L.d0 = dx1 * dy2 - dx2 * dy1;
-  L.n0 = zs * (dx1 * dz2 - dx2 * dz1);
-  L.d1 = di1 * dy2 - di2 * dy1;
-  L.n1 = zs * (di1 * dz2 - di2 * dz1);
+  L.d0 = mul32(dx1, dy2) - mul32(dx2, dy1);
+  L.n0 = zs * (mul32(dx1, dz2) - mul32(dx2, dz1));
+  L.d1 = mul32(di1, dy2) - mul32(di2, dy1);
+  L.n1 = zs * (mul32(di1, dz2) - mul32(di2, dz1));
   return L;
 }
 
@@ -130,10 +130,10 @@ __device__ __noinline__ int d_sign_slow(int4 P, int4 Q, int4 R) {
 
 // Perturbed sign of D(a, b, c) (xy orientation).
 __device__ __forceinline__ int d_sign(int4 P, int4 Q, int4 R) {
-  int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
-  int64_t D0 = ((int64_t)Q.x - P.x) * dy2 - ((int64_t)R.x - P.x) * dy1;
+  const int dy1 = dif32(Q.y, P.y), dy2 = dif32(R.y, P.y);
+  const int64_t D0 = mul32(dif32(Q.x, P.x), dy2) - mul32(dif32(R.x, P.x), dy1);
   if (D0) return D0 > 0 ? 1 : -1;
-  int64_t D1 = ((int64_t)Q.w - P.w) * dy2 - ((int64_t)R.w - P.w) * dy1;
+  const int64_t D1 = mul32(Q.w - P.w, dy2) - mul32(R.w - P.w, dy1);
   if (D1) return D1 > 0 ? 1 : -1;
   return d_sign_slow(P, Q, R);
 }

@@ -163,21 +163,27 @@ __device__ __noinline__ int tau_cmp_exact(const Coef& A, const Coef& B) {
 // ---------------------------------------------------------------------------
 // Fast path: standard part of tau in double.
 // ---------------------------------------------------------------------------
+// Coordinate differences fit int32 (|coord| <= 2^29; indices < 2^26), so the
+// orientation products are 32 x 32 -> 64-bit multiplies.  The subtraction is
+// done in unsigned arithmetic (defined wrap-around for inputs the range check
+// rejects: no merge runs on them).
+__device__ __forceinline__ int dif32(int a, int b) { return (int)((unsigned)a - (unsigned)b); }
+__device__ __forceinline__ int64_t mul32(int a, int b) { return (int64_t)a * (int64_t)b; }
 // Returns the real limit of tau as the epsilons vanish when it is finite and
 // one of the two leading cases holds (D0 != 0, or D0 = N0 = 0 and D1 != 0);
 // NaN otherwise (the exact path then decides every comparison).
 __device__ __forceinline__ double tau_std(int4 P, int4 Q, int4 R, int zs) {
-  int64_t dx1 = (int64_t)Q.x - P.x, dx2 = (int64_t)R.x - P.x;
-  int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
-  int64_t dz1 = (int64_t)Q.z - P.z, dz2 = (int64_t)R.z - P.z;
-  int64_t D0 = dx1 * dy2 - dx2 * dy1;
-  int64_t N0 = dx1 * dz2 - dx2 * dz1;
+  const int dx1 = dif32(Q.x, P.x), dx2 = dif32(R.x, P.x);
+  const int dy1 = dif32(Q.y, P.y), dy2 = dif32(R.y, P.y);
+  const int dz1 = dif32(Q.z, P.z), dz2 = dif32(R.z, P.z);
+  const int64_t D0 = mul32(dx1, dy2) - mul32(dx2, dy1);
+  const int64_t N0 = mul32(dx1, dz2) - mul32(dx2, dz1);
   if (D0 != 0) return (double)(zs * N0) / (double)D0;
   if (N0 != 0) return __builtin_nan("");
-  int64_t di1 = (int64_t)Q.w - P.w, di2 = (int64_t)R.w - P.w;
-  int64_t D1 = di1 * dy2 - di2 * dy1;
+  const int di1 = Q.w - P.w, di2 = R.w - P.w;
+  const int64_t D1 = mul32(di1, dy2) - mul32(di2, dy1);
   if (D1 == 0) return __builtin_nan("");
-  int64_t N1 = di1 * dz2 - di2 * dz1;
+  const int64_t N1 = mul32(di1, dz2) - mul32(di2, dz1);
   return (double)(zs * N1) / (double)D1;
 }
 
