@@ -192,7 +192,7 @@ def single(args, hull, workloads):
     ev.close()
 
     roofline = levels = None
-    S = min(sched.serial_levels, L) if sched.fused_levels == 0 else 0
+    S = min(sched.serial_levels, L)
     if golden is not None:
         stats = np.array(golden["level_stats_lower"]) + np.array(golden["level_stats_upper"])
         Bk = 4.0 * stats[:, 0] + 4.0 * stats[:, 1] + 28.0 * stats[:, 2]  # bytes per level
@@ -239,8 +239,7 @@ def single(args, hull, workloads):
                    else f"{args.workload}: n={n}",
                    "n": n, "faces": F, "runs": "lower+upper",
                    "schedule": {"serial_levels": sched.serial_levels,
-                                "walk_segment": sched.walk_segment,
-                                "fused_levels": sched.fused_levels}},
+                                "walk_segment": sched.walk_segment}},
         "bit_exact": bit_exact,
         "phase_ms": {"sort": round(sort_ms, 4), "merge_levels": [round(v, 4) for v in lvl],
                      "extract": round(extract_ms, 4)},

@@ -97,8 +97,8 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
  *                  paper's kernel, Sec. 3); the levels above split each merge
  *                  into time segments walked in parallel (default 9)
  *   walk_segment   child events per walk segment, >= 8 (default 8)
- *   fused_levels   0, or 7..9: the bottom levels of a single hull merged in
- *                  LDS tiles of 2^fused_levels points (default 0) */
+ *   fused_levels   reserved: pass 0 or -1
+ *   reserved       pass 0 */
 typedef struct hull_schedule_t {
   int32_t serial_levels;
   int32_t walk_segment;
@@ -108,8 +108,8 @@ typedef struct hull_schedule_t {
 
 /* The schedule the library uses when a call passes none (or leaves a field
  * at its default): the built-in defaults, overridden by the environment
- * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT and HULL_FUSED_LEVELS when
- * set.  Host, synchronous. */
+ * variables HULL_SERIAL_LEVELS and HULL_WALK_SEGMENT when set.  Host,
+ * synchronous. */
 int32_t hull_schedule_defaults(hull_schedule_t* out);
 
 /* Bytes of device workspace for hull_full_batched over H hulls of

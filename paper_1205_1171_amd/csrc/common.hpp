@@ -31,25 +31,28 @@ struct Header {
 };
 
 // One movie event: the face (a, w, b) of ranks a < w < b whose middle vertex w
-// enters (kind = 1) or leaves (kind = 0) the kinetic chain; the event time's
-// standard part is kept beside it in a parallel double array.
-struct Event {
+// enters (kind = 1) or leaves (kind = 0) the kinetic chain, and the standard
+// part of its time.  One 32-byte record, so that an event and its time come
+// in one access.
+struct __align__(16) Event {
   int a, w, b, kind;
+  double t;
+  double pad;
 };
 
 // Offsets (bytes) of every workspace region for n points in H hulls.
 struct Plan {
   size_t header, keys0, vals0, keys1, vals1, counts, partials, pts, hid, off1;
-  size_t pv0[2], nx0[2], pv[2], nx[2];
-  size_t ev[2][2], tau[2][2], len[2][2];  // [run][buffer]
+  size_t pv0[2], nx0[2], lk[2];
+  size_t ev[2][2], len[2][2];  // [run][buffer]
   // the level schedule (merge list, trailing blocks)
   size_t mcnt, moff, tcnt, toff, tlist, mlist;
   // parallel merge strategy, per run
   size_t cntR[2], cntL[2], offR[2], offL[2], curR[2], curL[2], claimR[2], claimL[2];
-  size_t entR[2], entL[2], entRt[2], entLt[2], ctr[2], touched[2];
+  size_t entR[2], entL[2], ctr[2], touched[2];
   size_t ecnt[2], eoff[2], cslot[2], cmerge[2];
   size_t segS[2], segBase[2], segMerge[2], segCnt[2], segOff[2], segUV[2];
-  size_t bev[2], btau[2], buv[2], nB[2], boff[2], uv0[2], surv[2], jb[2], pre[2];
+  size_t bev[2], buv[2], nB[2], boff[2], uv0[2], surv[2], jb[2], pre[2];
   size_t aR[2], aL[2], aT[2], wf[2];
   // face counts of the hulls of a batch
   size_t fcnt;

@@ -16,13 +16,10 @@ struct RunPtrs {
   const int4* pts;
   int* pv0;
   int* nx0;
-  int* pv;
-  int* nx;
+  int2* lk;  // working links of the level: (pv, nx) of each point
   const Event* ev_in;
-  const double* tau_in;
   const int* len_in;
   Event* ev_out;
-  double* tau_out;
   int* len_out;
   int zs;
 };
@@ -158,12 +155,12 @@ __device__ __forceinline__ int find_owner(const int* off, int count, int64_t x) 
   return lo;
 }
 
-__device__ __forceinline__ Cand cand_of(const Event* ev, const double* tau, int64_t q) {
-  Event E = ev[q];
+__device__ __forceinline__ Cand cand_of(const Event* ev, int64_t q) {
+  const Event& E = ev[q];
   Cand c;
   c.t = Tri{E.a, E.w, E.b};
   c.kind = E.kind;
-  c.st = tau[q];
+  c.st = E.t;
   return c;
 }
 
@@ -176,10 +173,8 @@ struct ParRun {
   int* pv0;
   int* nx0;
   const Event* ev_in;
-  const double* tau_in;
   const int* len_in;
   Event* ev_out;
-  double* tau_out;
   int* len_out;
   int* cntR;      // per point: # child events changing nx(p)
   int* cntL;      // per point: # child events changing pv(p)
@@ -191,9 +186,7 @@ struct ParRun {
   int* claimL;
   int stamp;      // this level's claim stamp: lists of other points are empty
   Event* entR;    // link-change events grouped by point, time-sorted (kind | slot << 1)
-  double* entRt;  // their times
   Event* entL;
-  double* entLt;
   int* ctr;       // [2] touched lists; [4..7] level totals: merges, child events,
                   // walk segments, bridge events
   int* touched;   // (point << 1 | side) of every allocated list
@@ -208,7 +201,6 @@ struct ParRun {
   int* segOff;    // exclusive scan of segCnt
   int2* segUV;    // per segment: the bridge at its start (found by the counting pass)
   Event* bev;     // bridge events of merge (s, e) at slots [2s, 2s + nB)
-  double* btau;
   int2* buv;      // (u, v) after each bridge event
   int* nB;        // per merge: # bridge events
   int* boff;      // exclusive scan of nB

@@ -34,8 +34,7 @@ namespace hull {
 
 __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int64_t e) {
   const int4* pts = R.pts;
-  int* pv = R.pv;
-  int* nx = R.nx;
+  int2* lk = R.lk;  // (pv, nx)
   const int zs = R.zs;
   const int nL = R.len_in[s], nR = R.len_in[m];
   if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m)) {
@@ -45,10 +44,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   }
   const Event* Lev = R.ev_in + 2 * s;
   const Event* Rev = R.ev_in + 2 * m;
-  const double* Ltau = R.tau_in + 2 * s;
-  const double* Rtau = R.tau_in + 2 * m;
   Event* out = R.ev_out + 2 * s;
-  double* out_tau = R.tau_out + 2 * s;
   const int64_t cap = 2 * (e - s);
 
   // 1. bridge at t = -inf
@@ -97,7 +93,14 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   T.t = Tri{-1, -1, -1};
   T.st = 0.0;
   T.kind = 0;
-  int nu = nx[u], pu = pv[u], pvv = pv[v], nv = nx[v];
+  int nu, pu, pvv, nv;
+  {
+    const int2 lu = lk[u], lv = lk[v];
+    pu = lu.x;
+    nu = lu.y;
+    pvv = lv.x;
+    nv = lv.y;
+  }
   // bridge best: slot (2..5, -1 = none) and its standard part
   int bbi = -1;
   double bbs = 0.0;
@@ -105,15 +108,15 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   bool ok2 = false, ok3 = false, ok4 = false, ok5 = false;
   unsigned dirty = 0xF;
   // the next event of each child, loaded one iteration ahead
-  Event EL{0, 0, 0, 0}, ER{0, 0, 0, 0};
+  int4 EL = make_int4(0, 0, 0, 0), ER = make_int4(0, 0, 0, 0);
   double tL = 0.0, tR = 0.0;
   if (nL > 0) {
-    EL = Lev[0];
-    tL = Ltau[0];
+    EL = *(const int4*)&Lev[0];
+    tL = Lev[0].t;
   }
   if (nR > 0) {
-    ER = Rev[0];
-    tR = Rtau[0];
+    ER = *(const int4*)&Rev[0];
+    tR = Rev[0].t;
   }
   const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
   for (int64_t it = 0;; ++it) {
@@ -183,7 +186,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     bool take_ = bi < 0;                                                 \
     if (!take_) {                                                        \
       Cand x_, y_;                                                       \
-      x_.t = Tri{(E_).a, (E_).w, (E_).b};                                \
+      x_.t = Tri{(E_).x, (E_).y, (E_).z};                                \
       x_.st = (T_);                                                      \
       x_.kind = 0;                                                       \
       y_.t = Tri{ba, bw, bb};                                            \
@@ -193,9 +196,9 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     }                                                                    \
     if (take_) {                                                         \
       bi = (IDX);                                                        \
-      ba = (E_).a;                                                       \
-      bw = (E_).w;                                                       \
-      bb = (E_).b;                                                       \
+      ba = (E_).x;                                                       \
+      bw = (E_).y;                                                       \
+      bb = (E_).z;                                                       \
       bs = (T_);                                                         \
     }                                                                    \
   }
@@ -207,8 +210,8 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     // (not carried through the selection: hipcc for gfx950 has dropped the
     // condition on such a carried field, taking the old value for lanes that
     // switch candidates)
-    if (bi == 0) bk = EL.kind;
-    else if (bi == 1) bk = ER.kind;
+    if (bi == 0) bk = EL.w;
+    else if (bi == 1) bk = ER.w;
     else bk = (bi == 2 || bi == 4) ? 1 : 0;
     T.t = Tri{ba, bw, bb};
     T.st = bs;
@@ -220,27 +223,21 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       // rest of this iteration
       if (bi == 0) {
         if (++i < nL) {
-          EL = Lev[i];
-          tL = Ltau[i];
+          EL = *(const int4*)&Lev[i];
+          tL = Lev[i].t;
         }
       } else {
         if (++j < nR) {
-          ER = Rev[j];
-          tR = Rtau[j];
+          ER = *(const int4*)&Rev[j];
+          tR = Rev[j].t;
         }
       }
       emit = bi == 0 ? (bw < u) : (bw > v);
       // the event sets nx(a) and pv(b) (and, inserting w, both links of w)
       const int na = bk ? bw : bb, pb = bk ? bw : ba;
-      if (bk) {  // insertion into the child's chain
-        nx[ba] = bw;
-        pv[bb] = bw;
-        pv[bw] = ba;
-        nx[bw] = bb;
-      } else {  // deletion
-        nx[ba] = bb;
-        pv[bb] = ba;
-      }
+      lk[ba].y = na;  // nx(a)
+      lk[bb].x = pb;  // pv(b)
+      if (bk) lk[bw] = make_int2(ba, bb);  // the inserted point's links
       // links of u and v it changed (w is never u or v when inserted)
       unsigned d = 0;
       if (ba == u) { nu = na; d |= 1u; }
@@ -253,13 +250,15 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       if (bi == 2 || bi == 3) {
         u = bi == 2 ? nu : pu;
         Pu = pts[u];
-        nu = nx[u];
-        pu = pv[u];
+        const int2 l = lk[u];
+        pu = l.x;
+        nu = l.y;
       } else {
         v = bi == 4 ? pvv : nv;
         Pv = pts[v];
-        pvv = pv[v];
-        nv = nx[v];
+        const int2 l = lk[v];
+        pvv = l.x;
+        nv = l.y;
       }
       dirty = 0xF;
     }
@@ -268,8 +267,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      out[k] = Event{ba, bw, bb, bk};
-      out_tau[k] = bs;
+      out[k] = Event{ba, bw, bb, bk, bs, 0.0};
       ++k;
     }
   }
@@ -294,88 +292,6 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
   merge_one(R, A.h, s, m, e);
 }
 
-// Bottom levels fused in LDS: one workgroup takes a tile of 2^KT consecutive
-// ranks (run blockIdx.y) through merge levels 1..KT with the lane-serial
-// merge, every array of the tile (points, links, both movie buffers) in LDS.
-// Only the tile's final movie and -inf links go back to HBM, in the layout
-// the level loop expects after KT levels (block start = tile start).
-template <int KT>
-__global__ void __launch_bounds__(256) k_merge_tile(LevelArgs A, const int4* __restrict__ gpts,
-                                                    int outbuf_is_b) {
-  constexpr int TP = 1 << KT;
-  __shared__ int4 P[TP];
-  __shared__ int pv0[TP], nx0[TP], pv[TP], nx[TP];
-  __shared__ Event ev[2][2 * TP];
-  __shared__ double tau[2][2 * TP];
-  __shared__ int len[2][TP];
-  const RunPtrs& G = A.run[blockIdx.y];
-  if (!G.pts) return;
-  const int64_t base = (int64_t)blockIdx.x * TP;
-  const int tn = (int)std::min<int64_t>(TP, A.n - base);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < TP; i += nt) {
-    if (i < tn) P[i] = gpts[base + i];
-    pv0[i] = kNil;
-    nx0[i] = kNil;
-    len[0][i] = 0;
-  }
-  __syncthreads();
-  RunPtrs R = G;
-  R.pts = P;
-  R.pv0 = pv0;
-  R.nx0 = nx0;
-  R.pv = pv;
-  R.nx = nx;
-  int buf = 0;
-  for (int k = 1; k <= KT; ++k) {
-    const int width = 1 << k, half = width >> 1;
-    for (int i = tid; i < tn; i += nt) {
-      pv[i] = pv0[i];
-      nx[i] = nx0[i];
-    }
-    __syncthreads();
-    R.ev_in = ev[buf];
-    R.tau_in = tau[buf];
-    R.len_in = len[buf];
-    R.ev_out = ev[buf ^ 1];
-    R.tau_out = tau[buf ^ 1];
-    R.len_out = len[buf ^ 1];
-    const int blocks = (tn + width - 1) / width;
-    for (int b = tid; b < blocks; b += nt) {
-      const int s = b * width, m = s + half, e = std::min(s + width, tn);
-      if (m >= e) {  // unpaired trailing block: passes through
-        int L = R.len_in[s];
-        for (int q = 0; q < L; ++q) {
-          R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
-          R.tau_out[2 * s + q] = R.tau_in[2 * s + q];
-        }
-        R.len_out[s] = L;
-      } else if (A.h->err) {
-        R.len_out[s] = 0;
-      } else {
-        merge_one(R, A.h, s, m, e);
-      }
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
-  // the tile is one block now: its movie, lengths and -inf links to HBM
-  const int L = len[buf][0];
-  Event* gev = G.ev_out + 2 * base;
-  double* gtau = G.tau_out + 2 * base;
-  (void)outbuf_is_b;
-  for (int q = tid; q < L; q += nt) {
-    Event E = ev[buf][q];
-    gev[q] = Event{E.a + (int)base, E.w + (int)base, E.b + (int)base, E.kind};
-    gtau[q] = tau[buf][q];
-  }
-  for (int i = tid; i < tn; i += nt) {
-    G.pv0[base + i] = pv0[i] == kNil ? kNil : pv0[i] + (int)base;
-    G.nx0[base + i] = nx0[i] == kNil ? kNil : nx0[i] + (int)base;
-  }
-  if (tid == 0) G.len_out[base] = L;
-}
-
 // The unpaired trailing block of a hull at this level keeps its movie: copy
 // it across (a hull already complete keeps its movie where it is).
 __global__ void __launch_bounds__(256) k_passthrough(LevelArgs A) {
@@ -386,10 +302,7 @@ __global__ void __launch_bounds__(256) k_passthrough(LevelArgs A) {
     const int64_t s = A.S.tlist[t];
     int len = R.len_in[s];
     if (A.h->err || len < 0 || len > 2 * A.half) len = 0;
-    for (int q = threadIdx.x; q < len; q += blockDim.x) {
-      R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
-      R.tau_out[2 * s + q] = R.tau_in[2 * s + q];
-    }
+    for (int q = threadIdx.x; q < len; q += blockDim.x) R.ev_out[2 * s + q] = R.ev_in[2 * s + q];
     if (threadIdx.x == 0) R.len_out[s] = len;
   }
 }
@@ -408,13 +321,10 @@ __global__ void __launch_bounds__(256) k_init_links(int* pv0, int* nx0, int* len
 
 __global__ void __launch_bounds__(256) k_copy_links(const int* __restrict__ pv0,
                                                     const int* __restrict__ nx0,
-                                                    int* __restrict__ pv, int* __restrict__ nx,
-                                                    int64_t n) {
+                                                    int2* __restrict__ lk, int64_t n) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    pv[p] = pv0[p];
-    nx[p] = nx0[p];
-  }
+       p += (int64_t)gridDim.x * blockDim.x)
+    lk[p] = make_int2(pv0[p], nx0[p]);
 }
 
 __device__ __forceinline__ int dev_levels(int64_t n) {
@@ -584,11 +494,11 @@ static int env_int(const char* name, int dflt) {
   return (e && *e) ? atoi(e) : dflt;
 }
 
-// The merge schedule: which levels run lane-serial, the walk segment length
-// and the LDS-fused bottom levels.  Unset fields take the environment
-// (HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT, HULL_FUSED_LEVELS), then defaults.
+// The merge schedule: which levels run lane-serial and the walk segment
+// length.  Unset fields take the environment (HULL_SERIAL_LEVELS,
+// HULL_WALK_SEGMENT), then defaults.
 struct Opts {
-  int serial_max, seg, fused;
+  int serial_max, seg;
 };
 
 static Opts resolve(const hull_schedule_t* sc) {
@@ -596,9 +506,6 @@ static Opts resolve(const hull_schedule_t* sc) {
   o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 9);
   o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 8);
   if (o.seg < 8) o.seg = 8;
-  o.fused = sc && sc->fused_levels >= 0 ? sc->fused_levels : env_int("HULL_FUSED_LEVELS", 0);
-  if (o.fused > 0) o.fused = o.fused < 7 ? 7 : (o.fused > 9 ? 9 : o.fused);
-  if (o.fused < 0) o.fused = 0;
   return o;
 }
 
@@ -631,8 +538,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     R.pts = on ? (const int4*)(ws + pl.pts) : nullptr;
     R.pv0 = (int*)(ws + pl.pv0[r]);
     R.nx0 = (int*)(ws + pl.nx0[r]);
-    R.pv = (int*)(ws + pl.pv[r]);
-    R.nx = (int*)(ws + pl.nx[r]);
+    R.lk = (int2*)(ws + pl.lk[r]);
     R.zs = r == 0 ? 1 : -1;
     ParRun& Q = P.run[r];
     Q.pts = R.pts;
@@ -649,8 +555,6 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.claimL = (int*)(ws + pl.claimL[r]);
     Q.entR = (Event*)(ws + pl.entR[r]);
     Q.entL = (Event*)(ws + pl.entL[r]);
-    Q.entRt = (double*)(ws + pl.entRt[r]);
-    Q.entLt = (double*)(ws + pl.entLt[r]);
     Q.ctr = (int*)(ws + pl.ctr[r]);
     Q.touched = (int*)(ws + pl.touched[r]);
     Q.ecnt = (int*)(ws + pl.ecnt[r]);
@@ -664,7 +568,6 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.segOff = (int*)(ws + pl.segOff[r]);
     Q.segUV = (int2*)(ws + pl.segUV[r]);
     Q.bev = (Event*)(ws + pl.bev[r]);
-    Q.btau = (double*)(ws + pl.btau[r]);
     Q.buv = (int2*)(ws + pl.buv[r]);
     Q.nB = (int*)(ws + pl.nB[r]);
     Q.boff = (int*)(ws + pl.boff[r]);
@@ -682,33 +585,8 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
   }
   int32_t* partials = (int32_t*)(ws + pl.partials);
   int buf = 0;
-  // levels 1..KT fused in LDS, one workgroup per tile of 2^KT ranks (a single
-  // hull, and only when at least KT levels are asked for)
-  int KT = opt.fused;
-  if (KT > levels || S.H != 1) KT = 0;
-  if (KT > 0) {
-    for (int r = 0; r < 2; ++r) {
-      RunPtrs& R = A.run[r];
-      R.ev_out = (Event*)(ws + pl.ev[r][KT & 1]);
-      R.tau_out = (double*)(ws + pl.tau[r][KT & 1]);
-      R.len_out = (int*)(ws + pl.len[r][KT & 1]);
-    }
-    if (events) (void)hipEventRecord(events[2], s);
-    const int64_t tiles = (n + (int64_t(1) << KT) - 1) >> KT;
-    const int4* gpts = (const int4*)(ws + pl.pts);
-    if (KT == 7)
-      hipLaunchKernelGGL(k_merge_tile<7>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
-    else if (KT == 8)
-      hipLaunchKernelGGL(k_merge_tile<8>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
-    else
-      hipLaunchKernelGGL(k_merge_tile<9>, dim3((unsigned)tiles, 2), dim3(256), 0, s, A, gpts, 0);
-    if (events)
-      for (int q = 3; q <= 2 * KT + 1; ++q) (void)hipEventRecord(events[q], s);
-    HULL_LAUNCH_CHECK();
-    buf = KT & 1;
-  }
   const unsigned hgrid = grid_for(S.H + 1, 1024);
-  for (int k = KT + 1; k <= levels; ++k) {
+  for (int k = 1; k <= levels; ++k) {
     A.width = int64_t(1) << k;
     A.half = A.width >> 1;
     const bool serial = k <= opt.serial_max;
@@ -722,21 +600,16 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     for (int r = 0; r < 2; ++r) {
       RunPtrs& R = A.run[r];
       R.ev_in = (const Event*)(ws + pl.ev[r][buf]);
-      R.tau_in = (const double*)(ws + pl.tau[r][buf]);
       R.len_in = (const int*)(ws + pl.len[r][buf]);
       R.ev_out = (Event*)(ws + pl.ev[r][buf ^ 1]);
-      R.tau_out = (double*)(ws + pl.tau[r][buf ^ 1]);
       R.len_out = (int*)(ws + pl.len[r][buf ^ 1]);
       ParRun& Q = P.run[r];
       Q.ev_in = R.ev_in;
-      Q.tau_in = R.tau_in;
       Q.len_in = R.len_in;
       Q.ev_out = R.ev_out;
-      Q.tau_out = R.tau_out;
       Q.len_out = R.len_out;
       if (R.pts && serial)
-        hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.pv,
-                           R.nx, n);
+        hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.lk, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
     if (serial) {
@@ -921,7 +794,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
   const hull::Opts o = hull::resolve(nullptr);
   out->serial_levels = o.serial_max;
   out->walk_segment = o.seg;
-  out->fused_levels = o.fused;
+  out->fused_levels = 0;
   out->reserved = 0;
   return HULL_OK;
 }

@@ -28,12 +28,12 @@
 namespace hull {
 
 // # of events among slots [base, base + len) strictly before X.
-__device__ int count_before(const int4* pts, const Event* ev, const double* tau, int64_t base,
-                            int len, const Cand& X, int zs) {
+__device__ int count_before(const int4* pts, const Event* ev, int64_t base, int len, const Cand& X,
+                            int zs) {
   int lo = 0, hi = len;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    Cand c = cand_of(ev, tau, base + mid);
+    Cand c = cand_of(ev, base + mid);
     if (ev_cmp(pts, c, X, zs) < 0) lo = mid + 1;
     else hi = mid;
   }
@@ -41,21 +41,18 @@ __device__ int count_before(const int4* pts, const Event* ev, const double* tau,
 }
 
 // Sort one point's entries by slot (= time order within the child movie).
-__device__ void sort_entries(Event* a, double* t, int k) {
+__device__ void sort_entries(Event* a, int k) {
   int gap = 1;
   while (gap < k / 3) gap = 3 * gap + 1;
   for (; gap > 0; gap /= 3)
     for (int i = gap; i < k; ++i) {
       Event x = a[i];
-      double y = t[i];
       int j = i;
       while (j >= gap && a[j - gap].kind > x.kind) {
         a[j] = a[j - gap];
-        t[j] = t[j - gap];
         j -= gap;
       }
       a[j] = x;
-      t[j] = y;
     }
 }
 
@@ -67,23 +64,23 @@ __device__ __forceinline__ int left_after(const Event& E, int p) {
   return p == E.b ? ((E.kind & 1) ? E.w : E.a) : E.a;
 }
 
-__device__ __forceinline__ Cand cand_entry(const Event* e, const double* t, int j) {
-  Event E = e[j];
+__device__ __forceinline__ Cand cand_entry(const Event* e, int j) {
+  const Event& E = e[j];
   Cand c;
   c.t = Tri{E.a, E.w, E.b};
   c.kind = E.kind & 1;
-  c.st = t[j];
+  c.st = E.t;
   return c;
 }
 
 // Position in a point's list of its first change strictly after T.
-__device__ int first_after(const ParRun& R, const Event* e, const double* t, int off, int cnt,
-                           bool haveT, const Cand& T) {
+__device__ int first_after(const ParRun& R, const Event* e, int off, int cnt, bool haveT,
+                           const Cand& T) {
   if (!haveT) return 0;
   int lo = 0, hi = cnt;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    Cand c = cand_entry(e, t, off + mid);
+    Cand c = cand_entry(e, off + mid);
     if (ev_cmp(R.pts, c, T, R.zs) > 0) hi = mid;
     else lo = mid + 1;
   }
@@ -106,8 +103,8 @@ __device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) 
   X.nR = hasR ? R.cntR[p] : 0;
   X.oL = hasL ? R.offL[p] : 0;
   X.nL = hasL ? R.cntL[p] : 0;
-  X.cr = first_after(R, R.entR, R.entRt, X.oR, X.nR, haveT, T);
-  X.cl = first_after(R, R.entL, R.entLt, X.oL, X.nL, haveT, T);
+  X.cr = first_after(R, R.entR, X.oR, X.nR, haveT, T);
+  X.cl = first_after(R, R.entL, X.oL, X.nL, haveT, T);
   X.nx = X.cr > 0 ? right_after(R.entR[X.oR + X.cr - 1], p) : R.nx0[p];
   X.pv = X.cl > 0 ? left_after(R.entL[X.oL + X.cl - 1], p) : R.pv0[p];
 }
@@ -118,12 +115,12 @@ __device__ int link_after(const ParRun& R, int p, bool right, bool haveT, const 
   if (right) {
     if (R.claimR[p] != R.stamp) return R.nx0[p];
     const int o = R.offR[p];
-    const int c = first_after(R, R.entR, R.entRt, o, R.cntR[p], haveT, T);
+    const int c = first_after(R, R.entR, o, R.cntR[p], haveT, T);
     return c > 0 ? right_after(R.entR[o + c - 1], p) : R.nx0[p];
   }
   if (R.claimL[p] != R.stamp) return R.pv0[p];
   const int o = R.offL[p];
-  const int c = first_after(R, R.entL, R.entLt, o, R.cntL[p], haveT, T);
+  const int c = first_after(R, R.entL, o, R.cntL[p], haveT, T);
   return c > 0 ? left_after(R.entL[o + c - 1], p) : R.pv0[p];
 }
 
@@ -158,7 +155,7 @@ __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
 // bridges after each move to `out_uv`).  Segment 0 also reports the -inf
 // bridge in `uv0`.
 __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e, int seg,
-                            int S, Event* out, double* out_tau, int2* out_uv, int cap,
+                            int S, Event* out, int2* out_uv, int cap,
                             int2* uv0, int2* start_uv, bool have_start) {
   const int4* pts = R.pts;
   const int zs = R.zs;
@@ -169,11 +166,11 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
   T.kind = 0;
   Tend = T;
   if (seg > 0) {
-    T = cand_of(R.ev_in, R.tau_in, boundary_slot(R, s, m, seg, S));
+    T = cand_of(R.ev_in, boundary_slot(R, s, m, seg, S));
     haveT = true;
   }
   if (seg + 1 < S) {
-    Tend = cand_of(R.ev_in, R.tau_in, boundary_slot(R, s, m, seg + 1, S));
+    Tend = cand_of(R.ev_in, boundary_slot(R, s, m, seg + 1, S));
     haveEnd = true;
   }
   // the bridge at the start of the segment: walk to the lower common tangent
@@ -256,10 +253,10 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
     if (U.pv != kNil) HULL_CONSIDER(1, make_cand(pts, U.pv, U.p, V.p, pts[U.pv], Pu, Pv, 0, zs));
     if (V.pv != kNil) HULL_CONSIDER(2, make_cand(pts, U.p, V.pv, V.p, Pu, pts[V.pv], Pv, 1, zs));
     if (V.nx != kNil) HULL_CONSIDER(3, make_cand(pts, U.p, V.p, V.nx, Pu, Pv, pts[V.nx], 0, zs));
-    if (U.cr < U.nR) HULL_CONSIDER(4, cand_entry(R.entR, R.entRt, U.oR + U.cr));
-    if (U.cl < U.nL) HULL_CONSIDER(5, cand_entry(R.entL, R.entLt, U.oL + U.cl));
-    if (V.cl < V.nL) HULL_CONSIDER(6, cand_entry(R.entL, R.entLt, V.oL + V.cl));
-    if (V.cr < V.nR) HULL_CONSIDER(7, cand_entry(R.entR, R.entRt, V.oR + V.cr));
+    if (U.cr < U.nR) HULL_CONSIDER(4, cand_entry(R.entR, U.oR + U.cr));
+    if (U.cl < U.nL) HULL_CONSIDER(5, cand_entry(R.entL, U.oL + U.cl));
+    if (V.cl < V.nL) HULL_CONSIDER(6, cand_entry(R.entL, V.oL + V.cl));
+    if (V.cr < V.nR) HULL_CONSIDER(7, cand_entry(R.entR, V.oR + V.cr));
 #undef HULL_CONSIDER
     Cand best;
     best.t = Tri{ba, bw, bb};
@@ -292,8 +289,7 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      out[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind};
-      out_tau[nb] = T.st;
+      out[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind, T.st, 0.0};
       out_uv[nb] = make_int2(U.p, V.p);
     }
     ++nb;
@@ -481,21 +477,16 @@ __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
   GRID_STRIDE(c, R.ctr[5]) {
     const int q = R.cslot[c];
     const Event E = R.ev_in[q];
-    const double t = R.tau_in[q];
-    const Event X{E.a, E.w, E.b, (q << 1) | E.kind};
+    const Event X{E.a, E.w, E.b, (q << 1) | E.kind, E.t, 0.0};
     int j = R.offR[E.a] + atomicAdd(&R.curR[E.a], 1);
     R.entR[j] = X;
-    R.entRt[j] = t;
     j = R.offL[E.b] + atomicAdd(&R.curL[E.b], 1);
     R.entL[j] = X;
-    R.entLt[j] = t;
     if (E.kind) {
       j = R.offR[E.w] + atomicAdd(&R.curR[E.w], 1);
       R.entR[j] = X;
-      R.entRt[j] = t;
       j = R.offL[E.w] + atomicAdd(&R.curL[E.w], 1);
       R.entL[j] = X;
-      R.entLt[j] = t;
     }
   }
 }
@@ -505,8 +496,8 @@ __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
   if (!R.pts || P.h->err) return;
   GRID_STRIDE(t, R.ctr[2]) {
     const int x = R.touched[t], p = x >> 1;
-    if (x & 1) sort_entries(R.entL + R.offL[p], R.entLt + R.offL[p], R.cntL[p]);
-    else sort_entries(R.entR + R.offR[p], R.entRt + R.offR[p], R.cntR[p]);
+    if (x & 1) sort_entries(R.entL + R.offL[p], R.cntL[p]);
+    else sort_entries(R.entR + R.offR[p], R.cntR[p]);
   }
 }
 
@@ -542,14 +533,14 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
       continue;
     }
     if (!write) {
-      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, nullptr, 0, nullptr,
+      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, 0, nullptr,
                                  &R.segUV[t], false);
       continue;
     }
     const int64_t off = R.segOff[t] - R.segOff[first];
     const int cap = (int)(2 * (e - s) - off);
-    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.btau + 2 * s + off,
-                 R.buv + 2 * s + off, cap, i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], true);
+    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.buv + 2 * s + off, cap,
+                 i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], true);
     if (i == 0) R.nB[g] = R.segOff[first + S] - R.segOff[first];
   }
 }
@@ -570,8 +561,8 @@ __global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
     const int q = R.cslot[c];
     const int64_t s = P.S.mlist[g].x, m = s + half;
     const bool isL = q < 2 * m;
-    const Cand x = cand_of(R.ev_in, R.tau_in, q);
-    const int j = count_before(R.pts, R.bev, R.btau, 2 * s, R.nB[g], x, R.zs);
+    const Cand x = cand_of(R.ev_in, q);
+    const int j = count_before(R.pts, R.bev, 2 * s, R.nB[g], x, R.zs);
     const int2 ref = j > 0 ? R.buv[2 * s + j - 1] : R.uv0[g];
     R.surv[c] = isL ? (x.t.w < ref.x) : (x.t.w > ref.y);
     R.jb[c] = j;
@@ -597,13 +588,13 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
       const int64_t s = se.x, m = s + half, e = se.y;
       const int nL = R.len_in[s], nR = R.len_in[m];
       const int c0 = R.eoff[g], cR = c0 + nL;
-      const Cand x = cand_of(R.ev_in, R.tau_in, q);
+      const Cand x = cand_of(R.ev_in, q);
       int64_t pos;
       if (q < 2 * m) {
-        const int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, nR, x, R.zs);
+        const int idx = count_before(R.pts, R.ev_in, 2 * m, nR, x, R.zs);
         pos = (R.pre[c] - R.pre[c0]) + (R.pre[cR + idx] - R.pre[cR]) + R.jb[c];
       } else {
-        const int idx = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, nL, x, R.zs);
+        const int idx = count_before(R.pts, R.ev_in, 2 * s, nL, x, R.zs);
         pos = (R.pre[c0 + idx] - R.pre[c0]) + (R.pre[c] - R.pre[cR]) + R.jb[c];
       }
       if (pos >= 2 * (e - s)) {
@@ -611,7 +602,6 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
         continue;
       }
       R.ev_out[2 * s + pos] = R.ev_in[q];
-      R.tau_out[2 * s + pos] = x.st;
     } else if (t < (int64_t)E + Bt) {
       if (err) continue;
       const int64_t b = t - E;
@@ -621,16 +611,15 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
       const int64_t s = se.x, m = s + half, e = se.y;
       const int nL = R.len_in[s], nR = R.len_in[m];
       const int c0 = R.eoff[g], cR = c0 + nL;
-      const Cand x = cand_of(R.bev, R.btau, 2 * s + j);
-      const int iL = count_before(R.pts, R.ev_in, R.tau_in, 2 * s, nL, x, R.zs);
-      const int iR = count_before(R.pts, R.ev_in, R.tau_in, 2 * m, nR, x, R.zs);
+      const Cand x = cand_of(R.bev, 2 * s + j);
+      const int iL = count_before(R.pts, R.ev_in, 2 * s, nL, x, R.zs);
+      const int iR = count_before(R.pts, R.ev_in, 2 * m, nR, x, R.zs);
       const int64_t pos = j + (R.pre[c0 + iL] - R.pre[c0]) + (R.pre[cR + iR] - R.pre[cR]);
       if (pos >= 2 * (e - s)) {
         atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
         continue;
       }
       R.ev_out[2 * s + pos] = R.bev[2 * s + j];
-      R.tau_out[2 * s + pos] = x.st;
     } else {
       const int g = (int)(t - E - Bt);
       const int2 se = P.S.mlist[g];

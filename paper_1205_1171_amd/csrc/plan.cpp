@@ -53,11 +53,9 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
   for (int r = 0; r < 2; ++r) {
     p.pv0[r] = take(nn * 4);
     p.nx0[r] = take(nn * 4);
-    p.pv[r] = take(nn * 4);
-    p.nx[r] = take(nn * 4);
+    p.lk[r] = take(nn * sizeof(int2));
     for (int b = 0; b < 2; ++b) {
       p.ev[r][b] = take(2 * nn * sizeof(Event));
-      p.tau[r][b] = take(2 * nn * sizeof(double));
       p.len[r][b] = take(nn * 4);
     }
     p.cntR[r] = take(nn * 4);
@@ -70,8 +68,6 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.claimL[r] = take(nn * 4);
     p.entR[r] = take(4 * nn * sizeof(Event));
     p.entL[r] = take(4 * nn * sizeof(Event));
-    p.entRt[r] = take(4 * nn * sizeof(double));
-    p.entLt[r] = take(4 * nn * sizeof(double));
     p.ctr[r] = take(4 * sizeof(int32_t));
     p.touched[r] = take(2 * nn * 4);
     p.ecnt[r] = take((p.mcap + 1) * 4);
@@ -85,7 +81,6 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.segOff[r] = take((p.seg_cap + 1) * 4);
     p.segUV[r] = take((p.seg_cap + 1) * sizeof(int2));
     p.bev[r] = take(2 * nn * sizeof(Event));
-    p.btau[r] = take(2 * nn * sizeof(double));
     p.buv[r] = take(2 * nn * sizeof(int2));
     p.nB[r] = take((p.mcap + 1) * 4);
     p.boff[r] = take((p.mcap + 1) * 4);

@@ -42,18 +42,15 @@ def ws(H):
 
 # Merge strategies: every level lane-serial, every level parallel (bridge walk
 # and scatter), and the default split between them.  All must give the same
-# movies and faces.
-# The parallel strategy is also run with walk segments of 8 child events, so
-# that most walks start from a tangent found at a segment boundary.
-# Bottom levels fused in LDS (HULL_FUSED_LEVELS) are checked against the
-# same oracle with every tile depth.
+# movies and faces.  The parallel strategy is also run with walk segments of
+# 8 child events, so that most walks start from a tangent found at a segment
+# boundary, and with a split after level 3.
 STRATEGIES = {
-    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_FUSED_LEVELS": "0"},
-    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "", "HULL_FUSED_LEVELS": "0"},
-    "parallel_seg8": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "8", "HULL_FUSED_LEVELS": "0"},
-    "fused7": {"HULL_SERIAL_LEVELS": "8", "HULL_WALK_SEGMENT": "64", "HULL_FUSED_LEVELS": "7"},
-    "fused9": {"HULL_SERIAL_LEVELS": "9", "HULL_WALK_SEGMENT": "", "HULL_FUSED_LEVELS": "9"},
-    "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_FUSED_LEVELS": ""},
+    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": ""},
+    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16"},
+    "parallel_seg8": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "8"},
+    "split3_seg64": {"HULL_SERIAL_LEVELS": "3", "HULL_WALK_SEGMENT": "64"},
+    "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": ""},
 }
 
 
@@ -199,7 +196,7 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_FUSED_LEVELS"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
