@@ -96,4 +96,19 @@ int32_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t len, int32_t
 int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
                            int64_t cap, int32_t* partials, hipStream_t s);
 
+// Several such scans (same add and cap, each its own device length) in one
+// set of launches.  partials must hold kMaxScanJobs * (cap / 4096 + 2) ints.
+constexpr int kMaxScanJobs = 8;
+struct ScanJob {
+  const int32_t* in;
+  int32_t* out;
+  const int32_t* d_len;
+};
+struct ScanJobs {
+  ScanJob j[kMaxScanJobs];
+  int count;
+};
+int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_t* partials,
+                                 hipStream_t s);
+
 }  // namespace hull

@@ -21,6 +21,7 @@
 //      binary searches).
 // The result is the same movie as the lane-serial merge, event for event.
 #include <algorithm>
+#include <initializer_list>
 
 #include "common.hpp"
 #include "events.hpp"
@@ -637,55 +638,59 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
   }
 }
 
-int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
-  const dim3 g2(kStrideBlocks, 2), b256(256);
-  hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
+// Scans of the same per-run arrays of both runs (and of several arrays) in
+// one set of launches.
+static ScanJobs jobs_of(const ParLevel& P, std::initializer_list<int> fields, int ctr_index) {
+  ScanJobs J{};
   for (int r = 0; r < 2; ++r) {
     const ParRun& R = P.run[r];
     if (!R.pts) continue;
-    int32_t rc = exclusive_scan_dev(R.ecnt, R.eoff, R.ctr + 4, 1, P.S.mcap + 1, partials, s);
-    if (!rc) rc = exclusive_scan_dev(R.segS, R.segBase, R.ctr + 4, 1, P.S.mcap + 1, partials, s);
-    if (rc) return rc;
+    for (int f : fields) {
+      int32_t* a = nullptr;
+      switch (f) {
+        case 0: J.j[J.count] = ScanJob{R.ecnt, R.eoff, R.ctr + ctr_index}; break;
+        case 1: J.j[J.count] = ScanJob{R.segS, R.segBase, R.ctr + ctr_index}; break;
+        case 2: a = R.aR; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index}; break;
+        case 3: a = R.aL; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index}; break;
+        case 4: a = R.aT; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index}; break;
+        case 5: J.j[J.count] = ScanJob{R.segCnt, R.segOff, R.ctr + ctr_index}; break;
+        case 6: J.j[J.count] = ScanJob{R.nB, R.boff, R.ctr + ctr_index}; break;
+        default: J.j[J.count] = ScanJob{R.surv, R.pre, R.ctr + ctr_index}; break;
+      }
+      ++J.count;
+    }
   }
+  return J;
+}
+
+int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
+  const dim3 g2(kStrideBlocks, 2), b256(256);
+  hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
+  // per merge: child events, walk segments (length: merges + 1)
+  int32_t rc = exclusive_scan_dev_multi(jobs_of(P, {0, 1}, 4), 1, P.S.mcap + 1, partials, s);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_par_totals, dim3(1, 2), dim3(64), 0, s, P);
   hipLaunchKernelGGL(k_par_enum, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_count, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_claim, g2, b256, 0, s, P);
-  for (int r = 0; r < 2; ++r) {
-    const ParRun& R = P.run[r];
-    if (!R.pts) continue;
-    int32_t rc = exclusive_scan_dev(R.aR, R.aR, R.ctr + 5, 1, P.ecap + 1, partials, s);
-    if (!rc) rc = exclusive_scan_dev(R.aL, R.aL, R.ctr + 5, 1, P.ecap + 1, partials, s);
-    if (!rc) rc = exclusive_scan_dev(R.aT, R.aT, R.ctr + 5, 1, P.ecap + 1, partials, s);
-    if (rc) return rc;
-  }
+  // per child event: list entries and lists it allocates (length: events + 1)
+  rc = exclusive_scan_dev_multi(jobs_of(P, {2, 3, 4}, 5), 1, P.ecap + 1, partials, s);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_par_place, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_fill, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_sort, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_segtable, g2, b256, 0, s, P);
   const dim3 gw(16384, 2), b64(64);
   hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 0);
-  for (int r = 0; r < 2; ++r) {
-    const ParRun& R = P.run[r];
-    if (!R.pts) continue;
-    int32_t rc = exclusive_scan_dev(R.segCnt, R.segOff, R.ctr + 6, 1, P.seg_cap + 1, partials, s);
-    if (rc) return rc;
-  }
+  rc = exclusive_scan_dev_multi(jobs_of(P, {5}, 6), 1, P.seg_cap + 1, partials, s);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 1);
-  for (int r = 0; r < 2; ++r) {
-    const ParRun& R = P.run[r];
-    if (!R.pts) continue;
-    int32_t rc = exclusive_scan_dev(R.nB, R.boff, R.ctr + 4, 1, P.S.mcap + 1, partials, s);
-    if (rc) return rc;
-  }
+  rc = exclusive_scan_dev_multi(jobs_of(P, {6}, 4), 1, P.S.mcap + 1, partials, s);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_par_btotal, dim3(1, 2), dim3(64), 0, s, P);
   hipLaunchKernelGGL(k_par_classify, g2, b256, 0, s, P);
-  for (int r = 0; r < 2; ++r) {
-    const ParRun& R = P.run[r];
-    if (!R.pts) continue;
-    int32_t rc = exclusive_scan_dev(R.surv, R.pre, R.ctr + 5, 1, P.ecap + 1, partials, s);
-    if (rc) return rc;
-  }
+  rc = exclusive_scan_dev_multi(jobs_of(P, {7}, 5), 1, P.ecap + 1, partials, s);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_par_scatter, g2, b256, 0, s, P);
   HULL_LAUNCH_CHECK();
   return HULL_OK;

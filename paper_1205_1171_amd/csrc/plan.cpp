@@ -26,7 +26,7 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
   // walk segments of one level: sum over merges of 1 + events / G, events <= 2n
   p.seg_cap = p.mcap + (2 * nn) / std::max(min_seg, 1) + 1;
   int64_t longest = std::max<int64_t>({p.count_len, 2 * nn + 1, p.seg_cap + 1, hh + 1});
-  p.partial_len = scan_partials_needed(longest) + 2;
+  p.partial_len = kMaxScanJobs * (scan_partials_needed(longest) + 2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;

@@ -291,25 +291,30 @@ __device__ __forceinline__ int64_t dev_len(const int32_t* d_len, int add, int64_
   return L < 0 ? 0 : (L > cap ? cap : L);
 }
 
+// Up to kMaxScanJobs scans of device-given lengths in the same three
+// launches (blockIdx.y = job); job j keeps its tile sums at partials +
+// j * pstride.
 __global__ void __launch_bounds__(kSortThreads)
-    k_scan_tile_sums_dev(const int32_t* __restrict__ in, const int32_t* d_len, int add,
-                         int64_t cap, int32_t* __restrict__ sums) {
-  const int64_t len = dev_len(d_len, add, cap);
+    k_scan_tile_sums_dev(ScanJobs J, int add, int64_t cap, int64_t pstride, int32_t* partials) {
+  const ScanJob& jb = J.j[blockIdx.y];
+  const int64_t len = dev_len(jb.d_len, add, cap);
   if ((int64_t)blockIdx.x * kScanBlock >= len) return;
   __shared__ int wsum[kSortThreads / 64];
   int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
   int s = 0;
   for (int j = 0; j < kScanItems; ++j)
-    if (base + j < len) s += in[base + j];
+    if (base + j < len) s += jb.in[base + j];
   int total;
   block_exclusive_scan(s, wsum, total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+  if (threadIdx.x == 0) partials[blockIdx.y * pstride + blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-    k_scan_sums_dev(int32_t* sums, const int32_t* d_len, int add, int64_t cap) {
-  const int64_t len = dev_len(d_len, add, cap);
+    k_scan_sums_dev(ScanJobs J, int add, int64_t cap, int64_t pstride, int32_t* partials) {
+  const ScanJob& jb = J.j[blockIdx.x];
+  const int64_t len = dev_len(jb.d_len, add, cap);
   const int64_t nsums = (len + kScanBlock - 1) / kScanBlock;
+  int32_t* sums = partials + blockIdx.x * pstride;
   __shared__ int wsum[kSortThreads / 64];
   int carry = 0;
   for (int64_t b = 0; b < nsums; b += kSortThreads) {
@@ -323,37 +328,49 @@ __global__ void __launch_bounds__(kSortThreads)
 }
 
 __global__ void __launch_bounds__(kSortThreads)
-    k_scan_tiles_dev(const int32_t* __restrict__ in, const int32_t* d_len, int add, int64_t cap,
-                     const int32_t* __restrict__ sums, int32_t* __restrict__ out) {
-  const int64_t len = dev_len(d_len, add, cap);
+    k_scan_tiles_dev(ScanJobs J, int add, int64_t cap, int64_t pstride,
+                     const int32_t* __restrict__ partials) {
+  const ScanJob& jb = J.j[blockIdx.y];
+  const int64_t len = dev_len(jb.d_len, add, cap);
   if ((int64_t)blockIdx.x * kScanBlock >= len) return;
   __shared__ int wsum[kSortThreads / 64];
   int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
   int v[kScanItems];
   int s = 0;
   for (int j = 0; j < kScanItems; ++j) {
-    v[j] = base + j < len ? in[base + j] : 0;
+    v[j] = base + j < len ? jb.in[base + j] : 0;
     s += v[j];
   }
   int total;
-  int run = block_exclusive_scan(s, wsum, total) + sums[blockIdx.x];
+  int run = block_exclusive_scan(s, wsum, total) + partials[blockIdx.y * pstride + blockIdx.x];
   for (int j = 0; j < kScanItems; ++j) {
-    if (base + j < len) out[base + j] = run;
+    if (base + j < len) jb.out[base + j] = run;
     run += v[j];
   }
 }
 
-int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
-                           int64_t cap, int32_t* partials, hipStream_t s) {
-  if (cap <= 0) return HULL_OK;
-  unsigned blocks = (unsigned)((cap + kScanBlock - 1) / kScanBlock);
-  hipLaunchKernelGGL(k_scan_tile_sums_dev, dim3(blocks), dim3(kSortThreads), 0, s, in, d_len, add,
-                     cap, partials);
-  hipLaunchKernelGGL(k_scan_sums_dev, dim3(1), dim3(kSortThreads), 0, s, partials, d_len, add, cap);
-  hipLaunchKernelGGL(k_scan_tiles_dev, dim3(blocks), dim3(kSortThreads), 0, s, in, d_len, add, cap,
-                     partials, out);
+int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_t* partials,
+                                 hipStream_t s) {
+  if (cap <= 0 || J.count <= 0) return HULL_OK;
+  if (J.count > kMaxScanJobs) return HULL_EINVAL;
+  const int64_t blocks = (cap + kScanBlock - 1) / kScanBlock;
+  const int64_t pstride = blocks + 1;
+  hipLaunchKernelGGL(k_scan_tile_sums_dev, dim3((unsigned)blocks, J.count), dim3(kSortThreads), 0,
+                     s, J, add, cap, pstride, partials);
+  hipLaunchKernelGGL(k_scan_sums_dev, dim3(J.count), dim3(kSortThreads), 0, s, J, add, cap,
+                     pstride, partials);
+  hipLaunchKernelGGL(k_scan_tiles_dev, dim3((unsigned)blocks, J.count), dim3(kSortThreads), 0, s,
+                     J, add, cap, pstride, partials);
   HULL_LAUNCH_CHECK();
   return HULL_OK;
+}
+
+int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
+                           int64_t cap, int32_t* partials, hipStream_t s) {
+  ScanJobs J{};
+  J.j[0] = ScanJob{in, out, d_len};
+  J.count = 1;
+  return exclusive_scan_dev_multi(J, add, cap, partials, s);
 }
 
 void init_header(Header* h, hipStream_t s) {
