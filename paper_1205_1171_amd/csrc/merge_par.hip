@@ -534,15 +534,16 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
       continue;
     }
     if (!write) {
-      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, 0, nullptr,
-                                 &R.segUV[t], false);
+      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, 0,
+                                 i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], false);
       continue;
     }
+    if (i == 0) R.nB[g] = R.segOff[first + S] - R.segOff[first];
+    if (R.segCnt[t] == 0) continue;  // nothing to write (the -inf bridge is known)
     const int64_t off = R.segOff[t] - R.segOff[first];
     const int cap = (int)(2 * (e - s) - off);
-    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.buv + 2 * s + off, cap,
-                 i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], true);
-    if (i == 0) R.nB[g] = R.segOff[first + S] - R.segOff[first];
+    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.buv + 2 * s + off, cap, nullptr,
+                 &R.segUV[t], true);
   }
 }
 
