@@ -21,6 +21,8 @@ Also reported on the same line:
   differentiation 256 clouds x 16,384 points: FP32 volume/area forward +
                   backward for all clouds in one launch each, against one
                   launch per cloud, with and without the batched hull first;
+  adjacency       face adjacency (half-edge twins) of the n = 2^24 hull's faces
+                  and of the 10,000-cloud batch's faces;
   cpu_baseline    the oracle (sequential C, one thread) on a bounded sample of
                   the n = 2^24 workload.
 
@@ -191,6 +193,7 @@ def single(args, hull, workloads):
     extract_ms /= args.steps
     ev.close()
 
+    adj_ms = adjacency_ms(hull, faces[:F])
     roofline = levels = None
     S = min(sched.serial_levels, L)
     if golden is not None:
@@ -245,8 +248,43 @@ def single(args, hull, workloads):
                      "extract": round(extract_ms, 4)},
         "roofline": roofline,
         "levels": levels,
+        "adjacency": {"faces": F, "ms": round(adj_ms, 4),
+                      "Mfaces_per_s": round(F / (adj_ms / 1e3) / 1e6, 1)},
     }
     return out, p
+
+
+def adjacency_ms(hull, faces, face_off=None, pt_off=None, reps=5):
+    """Average ms of hull_face_adjacency on a face set (workspace and output
+    allocated once, outside the timed calls)."""
+    import torch
+    L_ = hull.lib()
+    F = faces.shape[0]
+    faces = faces.contiguous()
+    adj = torch.empty((max(F, 1), 3), dtype=torch.int32, device="cuda")
+    info = torch.empty(2, dtype=torch.int64, device="cuda")
+    nb = ctypes.c_size_t(0)
+    L_.hull_adjacency_workspace_bytes(F, ctypes.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    H = 1 if face_off is None else face_off.numel() - 1
+    P = ctypes.c_void_p
+
+    def call():
+        rc = L_.hull_face_adjacency(P(faces.data_ptr()), F,
+                                    P(face_off.data_ptr()) if face_off is not None else None,
+                                    P(pt_off.data_ptr()) if pt_off is not None else None, H,
+                                    P(adj.data_ptr()), P(info.data_ptr()), P(ws.data_ptr()),
+                                    ws.numel(), sptr)
+        if rc:
+            raise hull.HullError(rc, "hull_face_adjacency")
+
+    call()
+    ms = timed(call, reps)
+    st, open_edges = (int(v) for v in info.cpu())
+    if st or open_edges:
+        raise RuntimeError(f"adjacency: status {st}, {open_edges} open edges")
+    return ms
 
 
 def batched(hull, workloads, autotune, reps, per_hull=True):
@@ -305,6 +343,8 @@ def batched(hull, workloads, autotune, reps, per_hull=True):
         run_per_hull(min(H, 200))  # warm-up
         ms_loop = timed(lambda: run_per_hull(H), 1)
         log(f"one launch per cloud: {ms_loop:.1f} ms")
+    # face adjacency (half-edge twins) of the batch's faces
+    adj_ms = adjacency_ms(hull, faces, face_off, torch.from_numpy(off).cuda())
     s = sched if sched is not None else hull.schedule_defaults()
     return {
         "workload": f"cfg4: {H} clouds, sizes floor(2^U), U ~ U[3,16], 50/50 ball/sphere of "
@@ -320,6 +360,8 @@ def batched(hull, workloads, autotune, reps, per_hull=True):
         "speedup_vs_one_launch_per_hull": round(ms_loop / ms_graph, 2) if ms_loop else None,
         "Mpoints_per_s": round(N / (ms_graph / 1e3) / 1e6, 2),
         "bit_exact": bit_exact,
+        "adjacency": {"faces": int(face_off[-1]), "ms": round(adj_ms, 3),
+                      "Mfaces_per_s": round(int(face_off[-1]) / (adj_ms / 1e3) / 1e6, 1)},
     }
 
 

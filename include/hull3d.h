@@ -178,6 +178,32 @@ int32_t hull_volume_area_bwd(const float* d_p, const int64_t* d_pt_off, const in
                              const int64_t* d_face_off, int32_t H, const float* d_gV,
                              const float* d_gA, float* d_grad_p, void* stream);
 
+/* Bytes of device workspace for hull_face_adjacency on F faces (host,
+ * synchronous). */
+int32_t hull_adjacency_workspace_bytes(int64_t F, size_t* bytes);
+
+/* Face adjacency (half-edge twins) of closed, consistently oriented surfaces,
+ * as hull_full and hull_full_batched return them: the connectivity of an
+ * edge-list structure (the paper's future work, Sec. "Conclusion").
+ *   d_faces    device int32 [F, 3]: face rows; edge k of row f runs from
+ *              vertex k to vertex (k + 1) mod 3
+ *   d_face_off device int64 [H + 1] face offsets of the clouds, and
+ *   d_pt_off   device int64 [H + 1] their point offsets (vertex indices are
+ *              within the cloud); both NULL for a single surface (H ignored)
+ *   d_adj      device int32 [F, 3] (written): adj[f][k] = the row of the face
+ *              holding the reverse edge (vertex k+1 -> vertex k) in the same
+ *              cloud, -1 if none
+ *   d_info     device int64 [2] (written): status (HULL_OK; HULL_ERANGE: a
+ *              vertex index outside its cloud; HULL_EINTERNAL: a directed
+ *              edge used twice, not a 2-manifold) and the number of edges
+ *              without a twin (0 for a closed surface)
+ *   d_ws       workspace of hull_adjacency_workspace_bytes(F) bytes
+ * A hash table of directed edges in the workspace: one insertion pass, one
+ * lookup pass (deterministic result). */
+int32_t hull_face_adjacency(const int32_t* d_faces, int64_t F, const int64_t* d_face_off,
+                            const int64_t* d_pt_off, int64_t H, int32_t* d_adj, int64_t* d_info,
+                            void* d_ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ Modules
 ``giftwrap``      an independent gift-wrapping hull under the same perturbation.
 ``validate``      canonical form, Euler count, closed-manifold and containment.
 ``volume_area``   FP64 hull volume and area and their gradients.
+``adjacency``     face adjacency (half-edge twins) of a face list.
 """
 import ctypes
 import os

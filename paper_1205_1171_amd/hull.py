@@ -75,6 +75,10 @@ def lib():
     L.hull_full_batched.restype = i32
     L.hull_schedule_defaults.argtypes = [ctypes.POINTER(Schedule)]
     L.hull_schedule_defaults.restype = i32
+    L.hull_adjacency_workspace_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+    L.hull_adjacency_workspace_bytes.restype = i32
+    L.hull_face_adjacency.argtypes = [P, i64, P, P, i64, P, P, P, sz, P]
+    L.hull_face_adjacency.restype = i32
     L.hull_movies.argtypes = [P, i64, i32, i32, P, P, P, P, P, sz, P]
     L.hull_movies.restype = i32
     L.hull_volume_area_fwd.argtypes = [P, P, P, P, i32, P, P, P]
@@ -90,7 +94,7 @@ def exported_symbols():
     L = lib()
     names = ["hull_strerror", "hull_last_hip_error", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
              "hull_workspace_bytes_batched", "hull_full_batched", "hull_schedule_defaults",
-             "hull_movies",
+             "hull_movies", "hull_adjacency_workspace_bytes", "hull_face_adjacency",
              "hull_volume_area_fwd", "hull_volume_area_bwd"]
     return [n for n in names if hasattr(L, n)]
 
@@ -222,6 +226,36 @@ def hull_batched_sync(xyz, offsets, schedule=None, ws=None):
     if st:
         raise HullError(st, "device")
     return faces[:F], face_off
+
+
+def face_adjacency(faces, face_off=None, pt_off=None, ws=None, stream=None):
+    """Half-edge twins of face rows (device int32 [F, 3] -> device int32
+    [F, 3]); face_off / pt_off: device int64 [H + 1] for a batch (vertex
+    indices within each cloud).  Blocking: returns (adj, open_edges)."""
+    import torch
+    if not (isinstance(faces, torch.Tensor) and faces.is_cuda and faces.dtype == torch.int32):
+        raise TypeError("faces must be a CUDA int32 tensor")
+    faces = faces.contiguous()
+    F = faces.shape[0]
+    dev = faces.device
+    adj = torch.empty((max(F, 1), 3), dtype=torch.int32, device=dev)
+    info = torch.empty(2, dtype=torch.int64, device=dev)
+    nb = ctypes.c_size_t(0)
+    rc = lib().hull_adjacency_workspace_bytes(F, ctypes.byref(nb))
+    if rc:
+        raise HullError(rc, "hull_adjacency_workspace_bytes")
+    wbuf = (ws or Workspace()).get(nb.value, dev)
+    H = 1 if face_off is None else face_off.numel() - 1
+    rc = lib().hull_face_adjacency(ctypes.c_void_p(faces.data_ptr()), F, _ptr(face_off),
+                                   _ptr(pt_off), H, ctypes.c_void_p(adj.data_ptr()),
+                                   ctypes.c_void_p(info.data_ptr()),
+                                   ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(), _stream(stream))
+    if rc:
+        raise HullError(rc, "hull_face_adjacency")
+    st, open_edges = (int(v) for v in info.cpu())
+    if st:
+        raise HullError(st, "device")
+    return adj[:F], open_edges
 
 
 def movies(xyz, run, level, ws=None):

@@ -115,3 +115,20 @@ def test_batched_argument_errors(L):
     assert L.hull_workspace_bytes_batched(-1, 1, ctypes.byref(out)) == hull.HULL_EINVAL
     # more hulls need more schedule space
     assert hull.workspace_bytes_batched(1000, 100) > hull.workspace_bytes_batched(1000, 1)
+
+
+def test_adjacency_argument_errors(L):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    out = ctypes.c_size_t(0)
+    assert L.hull_adjacency_workspace_bytes(-1, ctypes.byref(out)) == hull.HULL_EINVAL
+    assert L.hull_adjacency_workspace_bytes(100, ctypes.byref(out)) == hull.HULL_OK
+    ws = out.value
+    assert ws >= 16 * 600
+    f = L.hull_face_adjacency
+    assert f(None, 100, None, None, 1, fake, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, None, None, 1, None, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, None, None, 1, fake, None, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, fake, None, 1, fake, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, fake, fake, 0, fake, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, None, None, 1, fake, fake, fake, ws - 1, None) == hull.HULL_EWORKSPACE
