@@ -14,6 +14,8 @@ Also reported on the same line:
                   of its launches on the library's stream in the timed steps;
   levels          the same figure for every merge level (the parallel levels
                   are several kernels each, timed as a whole);
+  other_single_hulls  Mpoints/s and bit-exact flags on n = 4096 and the
+                  n = 2^20 sphere and ball;
   batched         10,000 ragged clouds (7.3e7 points) in one hull_full_batched
                   call captured in a HIP graph, against one hull_full launch
                   per cloud on the same stream (hulls/s), schedule from the
@@ -27,7 +29,8 @@ Also reported on the same line:
                   the n = 2^24 workload.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
-                       [--no-batched] [--no-diff] [--no-per-hull] [--no-cpu]
+                       [--no-singles] [--no-batched] [--no-diff] [--no-per-hull]
+                       [--no-cpu]
 """
 import argparse
 import ctypes
@@ -246,6 +249,10 @@ def single(args, hull, workloads):
         "bit_exact": bit_exact,
         "phase_ms": {"sort": round(sort_ms, 4), "merge_levels": [round(v, 4) for v in lvl],
                      "extract": round(extract_ms, 4)},
+        # sort: range pass 12 B/pt, 3 radix passes of 16 B/pt (key + index read
+        # and written), gather 12 B/pt read + 16 B/pt written (22-bit keys)
+        "sort": {"ms": round(sort_ms, 4), "algorithmic_bytes": 88.0 * n,
+                 "GBps": round(88.0 * n / (sort_ms / 1e3) / 1e9, 1)},
         "roofline": roofline,
         "levels": levels,
         "adjacency": {"faces": F, "ms": round(adj_ms, 4),
@@ -285,6 +292,43 @@ def adjacency_ms(hull, faces, face_off=None, pt_off=None, reps=5):
     if st or open_edges:
         raise RuntimeError(f"adjacency: status {st}, {open_edges} open edges")
     return ms
+
+
+def other_singles(hull, workloads, reps=5):
+    """Mpoints/s of hull_full on the other single-hull workloads, each
+    checked against the oracle's digest."""
+    import torch
+    from oracle import validate
+    L_ = hull.lib()
+    out = {}
+    for name in ("cfg1", "cfg2_sphere", "cfg2_ball"):
+        p = getattr(workloads, name)()
+        n = len(p)
+        x = torch.from_numpy(p).cuda()
+        faces = torch.empty((2 * n, 3), dtype=torch.int32, device="cuda")
+        info = torch.zeros(2, dtype=torch.int64, device="cuda")
+        ws = torch.empty(hull.workspace_bytes(n), dtype=torch.uint8, device="cuda")
+        sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+        def call():
+            rc = L_.hull_full(ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(faces.data_ptr()),
+                              2 * n, ctypes.c_void_p(info.data_ptr()),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), sptr)
+            if rc:
+                raise hull.HullError(rc, "hull_full")
+
+        call()
+        call()
+        st, F = (int(v) for v in info.cpu())
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", f"{name}.json")))
+        exact = (st == 0 and F == g["F"] and hashlib.sha256(validate.canonical(
+            faces[:F].cpu().numpy()).astype("<i4").tobytes()).hexdigest() == g["sha256_full"])
+        ms = timed(call, reps)
+        out[name] = {"n": n, "faces": F, "ms": round(ms, 4),
+                     "Mpoints_per_s": round(n / (ms / 1e3) / 1e6, 2), "bit_exact": exact}
+        log(f"{name}: {out[name]}")
+        del x, faces, ws
+    return out
 
 
 def batched(hull, workloads, autotune, reps, per_hull=True):
@@ -464,6 +508,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-singles", action="store_true",
+                    help="skip the n = 4096 and n = 2^20 single-hull lines")
     ap.add_argument("--no-per-hull", action="store_true",
                     help="skip the one-launch-per-cloud comparison (for short profiles)")
     args = ap.parse_args()
@@ -475,6 +521,8 @@ def main():
     from paper_1205_1171_amd import autotune, hull, workloads
     hull.lib()
     out, p = single(args, hull, workloads)
+    if not args.no_singles:
+        out["other_single_hulls"] = other_singles(hull, workloads)
     if not args.no_batched:
         out["batched"] = batched(hull, workloads, autotune, reps=3,
                                  per_hull=not args.no_per_hull)
