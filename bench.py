@@ -16,6 +16,8 @@ Also reported on the same line:
                   are several kernels each, timed as a whole);
   other_single_hulls  Mpoints/s and bit-exact flags on n = 4096 and the
                   n = 2^20 sphere and ball;
+  delaunay        2-d Delaunay by lifting (lower hull of (x, y, x^2 + y^2)) on
+                  2^18 points, Mpoints/s and bit-exact flag;
   batched         10,000 ragged clouds (7.3e7 points) in one hull_full_batched
                   call captured in a HIP graph, against one hull_full launch
                   per cloud on the same stream (hulls/s), schedule from the
@@ -331,6 +333,43 @@ def other_singles(hull, workloads, reps=5):
     return out
 
 
+def delaunay_line(hull, workloads, reps=5):
+    """Delaunay by lifting on 2^18 points of [-2^14, 2^14]^2: Mpoints/s and
+    the bit-exact flag against the oracle's digest."""
+    import torch
+    from oracle import validate
+    L_ = hull.lib()
+    p = workloads.planar()
+    n = len(p)
+    x = torch.from_numpy(p).cuda()
+    tris = torch.empty((2 * n, 3), dtype=torch.int32, device="cuda")
+    info = torch.zeros(2, dtype=torch.int64, device="cuda")
+    nb = ctypes.c_size_t(0)
+    L_.hull_delaunay_workspace_bytes(n, ctypes.byref(nb))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call():
+        rc = L_.hull_delaunay(ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(tris.data_ptr()),
+                              2 * n, ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), sptr)
+        if rc:
+            raise hull.HullError(rc, "hull_delaunay")
+
+    call()
+    st, T = (int(v) for v in info.cpu())
+    exact = None
+    gpath = os.path.join(ROOT, "tests", "golden", "planar.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        exact = (st == 0 and T == g["T"] and hashlib.sha256(validate.canonical(
+            tris[:T].cpu().numpy()).astype("<i4").tobytes()).hexdigest() == g["sha256"])
+    ms = timed(call, reps)
+    return {"workload": f"planar: {n} distinct points uniform in [-2^14, 2^14]^2", "n": n,
+            "triangles": T, "ms": round(ms, 4), "Mpoints_per_s": round(n / (ms / 1e3) / 1e6, 2),
+            "bit_exact": exact}
+
+
 def batched(hull, workloads, autotune, reps, per_hull=True):
     """cfg4: one graph-captured batched call against one call per cloud."""
     import numpy as np
@@ -523,6 +562,7 @@ def main():
     out, p = single(args, hull, workloads)
     if not args.no_singles:
         out["other_single_hulls"] = other_singles(hull, workloads)
+        out["delaunay"] = delaunay_line(hull, workloads)
     if not args.no_batched:
         out["batched"] = batched(hull, workloads, autotune, reps=3,
                                  per_hull=not args.no_per_hull)

@@ -204,6 +204,26 @@ int32_t hull_face_adjacency(const int32_t* d_faces, int64_t F, const int64_t* d_
                             const int64_t* d_pt_off, int64_t H, int32_t* d_adj, int64_t* d_info,
                             void* d_ws, size_t ws_bytes, void* stream);
 
+/* Bytes of device workspace for hull_delaunay on n points (host,
+ * synchronous). */
+int32_t hull_delaunay_workspace_bytes(int64_t n, size_t* bytes);
+
+/* 2-d Delaunay triangulation by lifting: the lower hull of (x, y, x^2 + y^2)
+ * (the hull method of Sec. 2 and 3 unchanged; Sec. "Conclusion" names such
+ * follow-on algorithms).
+ *   d_xy    device int32 [n, 2], |x|, |y| <= 2^14 (so that x^2 + y^2 stays in
+ *           the hull's exact range; otherwise HULL_ERANGE in d_info[0])
+ *   d_tris  device int32 [cap, 3], cap >= 2n (written: first T rows):
+ *           triangles of input indices, counter-clockwise in the plane
+ *   d_info  device int64 [2]: status, T
+ *   d_ws    workspace of hull_delaunay_workspace_bytes(n) bytes
+ * Ties (cocircular or collinear points, duplicates) are decided by the hull's
+ * symbolic perturbation: the result is the Delaunay triangulation of the
+ * perturbed points (unique; zero-area triangles possible for degenerate
+ * input; T = 2n - h - 2 with h points on the perturbed convex hull). */
+int32_t hull_delaunay(const int32_t* d_xy, int64_t n, int32_t* d_tris, int64_t cap, int64_t* d_info,
+                      void* d_ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

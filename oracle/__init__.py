@@ -17,6 +17,7 @@ Modules
 ``validate``      canonical form, Euler count, closed-manifold and containment.
 ``volume_area``   FP64 hull volume and area and their gradients.
 ``adjacency``     face adjacency (half-edge twins) of a face list.
+``delaunay``      2-d Delaunay by lifting, and the in-circle pin.
 """
 import ctypes
 import os

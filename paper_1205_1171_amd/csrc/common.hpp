@@ -80,6 +80,12 @@ void note_hip_error(hipError_t e);
 // see the call's own launches only.
 inline void clear_stale_hip_error() { (void)hipGetLastError(); }
 
+// One hull (lower and/or upper run) of n points: sort, every merge level,
+// faces (the body of hull_lower / hull_full).
+int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
+                  void* const* events, int32_t nevents);
+
 // Clear the device status words (a kernel, so that the call can be captured).
 void init_header(Header* h, hipStream_t s);
 

@@ -79,6 +79,10 @@ def lib():
     L.hull_adjacency_workspace_bytes.restype = i32
     L.hull_face_adjacency.argtypes = [P, i64, P, P, i64, P, P, P, sz, P]
     L.hull_face_adjacency.restype = i32
+    L.hull_delaunay_workspace_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+    L.hull_delaunay_workspace_bytes.restype = i32
+    L.hull_delaunay.argtypes = [P, i64, P, i64, P, P, sz, P]
+    L.hull_delaunay.restype = i32
     L.hull_movies.argtypes = [P, i64, i32, i32, P, P, P, P, P, sz, P]
     L.hull_movies.restype = i32
     L.hull_volume_area_fwd.argtypes = [P, P, P, P, i32, P, P, P]
@@ -95,6 +99,7 @@ def exported_symbols():
     names = ["hull_strerror", "hull_last_hip_error", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
              "hull_workspace_bytes_batched", "hull_full_batched", "hull_schedule_defaults",
              "hull_movies", "hull_adjacency_workspace_bytes", "hull_face_adjacency",
+             "hull_delaunay_workspace_bytes", "hull_delaunay",
              "hull_volume_area_fwd", "hull_volume_area_bwd"]
     return [n for n in names if hasattr(L, n)]
 
@@ -256,6 +261,35 @@ def face_adjacency(faces, face_off=None, pt_off=None, ws=None, stream=None):
     if st:
         raise HullError(st, "device")
     return adj[:F], open_edges
+
+
+def delaunay(xy, ws=None, stream=None):
+    """Delaunay triangles (device int32 [T, 3], counter-clockwise) of the
+    CUDA int32 points xy [n, 2], |x|, |y| <= 2^14.  Blocking (checked)."""
+    import torch
+    if not (isinstance(xy, torch.Tensor) and xy.is_cuda and xy.dtype == torch.int32):
+        raise TypeError("points must be a CUDA int32 tensor")
+    if xy.dim() != 2 or xy.shape[1] != 2 or not xy.is_contiguous():
+        raise ValueError("points must be a contiguous [n, 2] tensor")
+    n = xy.shape[0]
+    dev = xy.device
+    cap = max(2 * n, 1)
+    tris = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+    info = torch.empty(2, dtype=torch.int64, device=dev)
+    nb = ctypes.c_size_t(0)
+    rc = lib().hull_delaunay_workspace_bytes(n, ctypes.byref(nb))
+    if rc:
+        raise HullError(rc, "hull_delaunay_workspace_bytes")
+    wbuf = (ws or Workspace()).get(nb.value, dev)
+    rc = lib().hull_delaunay(ctypes.c_void_p(xy.data_ptr()), n, ctypes.c_void_p(tris.data_ptr()), cap,
+                             ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()),
+                             wbuf.numel(), _stream(stream))
+    if rc:
+        raise HullError(rc, "hull_delaunay")
+    st, T = (int(v) for v in info.cpu())
+    if st:
+        raise HullError(st, "device")
+    return tris[:T]
 
 
 def movies(xyz, run, level, ws=None):

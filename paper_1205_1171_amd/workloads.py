@@ -192,3 +192,21 @@ def moment_curve(t0=-100, t1=100):
     """Points (t, t^2, t^3): every one a vertex of their hull (cyclic polytope)."""
     t = np.arange(t0, t1 + 1, dtype=np.int64)
     return np.stack([t, t * t, t * t * t], axis=1).astype(np.int32)
+
+
+def planar(n=1 << 18):
+    """Delaunay workload: n distinct int32 points uniform in [-2^14, 2^14]^2
+    (the lifting range), [n, 2]."""
+    rng = rng_for(6)
+    draw = lambda r, k: r.integers(-(1 << 14), 1 << 14, size=(k, 2), endpoint=True)
+    p = draw(rng, n)
+    for _ in range(1000):
+        key = (p[:, 0] + (1 << 15)) * (1 << 16) + (p[:, 1] + (1 << 15))
+        _, first = np.unique(key, return_index=True)
+        dup = np.ones(n, dtype=bool)
+        dup[first] = False
+        d = np.nonzero(dup)[0]
+        if len(d) == 0:
+            break
+        p[d] = draw(rng, len(d))
+    return np.ascontiguousarray(p.astype(np.int32))

@@ -12,7 +12,10 @@ records, per cloud in cloud order, the oracle's face count, and the SHA-256
 of the concatenation of every cloud's canonical face array (indices local to
 the cloud).
 
-usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3 cfg4
+For the Delaunay workload (planar: 2^18 points in [-2^14, 2^14]^2) it
+records the SHA-256 of the oracle's canonical triangle array.
+
+usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3 cfg4 planar
 (the lower and upper runs go to two processes; the clouds of cfg4 to a pool)
 """
 import hashlib
@@ -88,7 +91,28 @@ def make_batched(name, workers):
     print(name, rec["F"], rec["oracle_seconds_cpu"], rec["oracle_seconds_wall"], flush=True)
 
 
+def make_delaunay(name):
+    """The Delaunay workload: the oracle's lifted lower hull, CCW triangles."""
+    from oracle import delaunay as dl
+    p = workloads.planar()
+    t = time.time()
+    tris = dl.delaunay(p)
+    rec = {
+        "config": name,
+        "n": int(len(p)),
+        "input_sha256": hashlib.sha256(np.ascontiguousarray(p, dtype="<i4").tobytes()).hexdigest(),
+        "T": int(len(tris)),
+        "sha256": digest(tris),
+        "oracle_seconds": time.time() - t,
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(name, rec["T"], rec["oracle_seconds"], flush=True)
+
+
 def make(name):
+    if name == "planar":
+        return make_delaunay(name)
     if name == "cfg4":
         return make_batched(name, int(os.environ.get("GOLDEN_WORKERS", "6")))
     p = MAKERS[name]()

@@ -132,3 +132,18 @@ def test_adjacency_argument_errors(L):
     assert f(fake, 100, fake, None, 1, fake, fake, fake, ws, None) == hull.HULL_EINVAL
     assert f(fake, 100, fake, fake, 0, fake, fake, fake, ws, None) == hull.HULL_EINVAL
     assert f(fake, 100, None, None, 1, fake, fake, fake, ws - 1, None) == hull.HULL_EWORKSPACE
+
+
+def test_delaunay_argument_errors(L):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    out = ctypes.c_size_t(0)
+    assert L.hull_delaunay_workspace_bytes(100, ctypes.byref(out)) == hull.HULL_OK
+    assert out.value > hull.workspace_bytes(100)
+    ws = out.value
+    f = L.hull_delaunay
+    assert f(None, 100, fake, 200, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, fake, 199, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, -1, fake, 200, fake, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, fake, 200, None, fake, ws, None) == hull.HULL_EINVAL
+    assert f(fake, 100, fake, 200, fake, fake, ws - 1, None) == hull.HULL_EWORKSPACE

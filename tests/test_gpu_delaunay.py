@@ -1,0 +1,81 @@
+"""GPU parity of hull_delaunay (lifted lower hull) against the oracle's
+Delaunay triangulation: canonical triangle sets bit-exact on random,
+degenerate (grid, collinear, duplicate) and full-size inputs."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import delaunay as dl
+from oracle import validate
+from paper_1205_1171_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    from paper_1205_1171_amd import hull
+    assert torch.cuda.is_available()
+    hull.lib()
+    return hull
+
+
+def gpu_tris(H, p, ws=None):
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(p, dtype=np.int32).reshape(-1, 2)).cuda()
+    return H.delaunay(x, ws=ws).cpu().numpy()
+
+
+def same(a, b):
+    a, b = validate.canonical(a), validate.canonical(b)
+    return a.shape == b.shape and bool((a == b).all())
+
+
+def test_small_and_degenerate(H):
+    rng = np.random.default_rng(12)
+    ws = H.Workspace()
+    cases = [np.zeros((0, 2)), np.array([[0, 0]]), np.array([[0, 0], [1, 1]]),
+             np.array([[0, 0], [3, 0], [0, 5]]),                          # one triangle
+             np.array([[i, 2 * i] for i in range(9)]),                     # collinear
+             np.array([(x, y) for x in range(7) for y in range(6)]),       # cocircular grid
+             np.array([[0, 0]] * 5 + [[4, 1], [2, 7]])]                    # duplicates
+    for t in range(24):
+        n = int(rng.integers(3, 2500))
+        r = [3, 50, 1 << 14][t % 3]
+        cases.append(rng.integers(-r, r, size=(n, 2), endpoint=True))
+    for t, p in enumerate(cases):
+        say("delaunay case", t, len(p))
+        got = gpu_tris(H, p, ws)
+        assert same(got, dl.delaunay(p)), t
+        if len(got):
+            assert all(o >= 0 for o in dl.orient(p, got)), t
+
+
+def test_range_error(H):
+    import torch
+    p = np.array([[0, 0], [1 << 14, 0], [0, (1 << 14) + 1], [5, 5]], dtype=np.int32)
+    with pytest.raises(H.HullError) as e:
+        H.delaunay(torch.from_numpy(p).cuda())
+    assert e.value.code == H.HULL_ERANGE
+    p[2, 1] = -(1 << 14)
+    assert same(gpu_tris(H, p), dl.delaunay(p))
+
+
+def test_full_size_digest(H):
+    rec = json.load(open(os.path.join(GOLDEN, "planar.json")))
+    p = workloads.planar()
+    assert hashlib.sha256(np.ascontiguousarray(p, dtype="<i4").tobytes()).hexdigest() == rec["input_sha256"]
+    say("delaunay full size", len(p))
+    t = gpu_tris(H, p)
+    assert len(t) == rec["T"]
+    assert hashlib.sha256(validate.canonical(t).astype("<i4").tobytes()).hexdigest() == rec["sha256"]
