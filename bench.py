@@ -326,8 +326,21 @@ def other_singles(hull, workloads, reps=5):
         exact = (st == 0 and F == g["F"] and hashlib.sha256(validate.canonical(
             faces[:F].cpu().numpy()).astype("<i4").tobytes()).hexdigest() == g["sha256_full"])
         ms = timed(call, reps)
+        # the same hull through the batched entry point (one cloud) captured
+        # in a HIP graph: no per-kernel launch cost
+        bh = hull.BatchedHull(x, [0, n])
+        bh.capture()
+        bh.replay()
+        ms_g = timed(bh.replay, reps)
+        fg, _ = bh.result()
+        same = fg.shape[0] == F and hashlib.sha256(validate.canonical(
+            fg.cpu().numpy()).astype("<i4").tobytes()).hexdigest() == g["sha256_full"]
         out[name] = {"n": n, "faces": F, "ms": round(ms, 4),
-                     "Mpoints_per_s": round(n / (ms / 1e3) / 1e6, 2), "bit_exact": exact}
+                     "Mpoints_per_s": round(n / (ms / 1e3) / 1e6, 2), "bit_exact": exact,
+                     "ms_graph": round(ms_g, 4),
+                     "Mpoints_per_s_graph": round(n / (ms_g / 1e3) / 1e6, 2),
+                     "bit_exact_graph": same}
+        del bh
         log(f"{name}: {out[name]}")
         del x, faces, ws
     return out

@@ -211,3 +211,39 @@ def test_full_size_digest(H, ws, name):
     assert len(g) == rec["F"]
     assert hashlib.sha256(validate.canonical(g).astype("<i4").tobytes()).hexdigest() == rec["sha256_full"]
     assert validate.euler_ok(g) and validate.manifold_ok(g)
+
+
+def test_timed_entry_point_matches(H, ws):
+    """hull_full_timed: the same faces as hull_full, and its events bracket
+    every phase in order (non-negative times summing to the whole call)."""
+    import ctypes
+    import torch
+    import bench
+    p = workloads.cube(np.random.default_rng(4), 20000, 1 << 20)
+    n = len(p)
+    x = torch.from_numpy(p).cuda()
+    L = bench.levels_for(n)
+    nev = 2 * L + 3
+    ev = bench.Events(nev)
+    faces = torch.empty((2 * n, 3), dtype=torch.int32, device="cuda")
+    info = torch.zeros(2, dtype=torch.int64, device="cuda")
+    wsb = torch.empty(H.workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    sptr = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rc = H.lib().hull_full_timed(ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(faces.data_ptr()),
+                                 2 * n, ctypes.c_void_p(info.data_ptr()),
+                                 ctypes.c_void_p(wsb.data_ptr()), wsb.numel(), sptr,
+                                 ctypes.cast(ev.arr, ctypes.c_void_p), nev)
+    assert rc == 0
+    torch.cuda.synchronize()
+    st, F = (int(v) for v in info.cpu())
+    assert st == 0 and same(faces[:F].cpu().numpy(), oracle.hull(p))
+    parts = [ev.ms(q, q + 1) for q in range(nev - 1)]
+    assert all(t >= 0 for t in parts)
+    assert abs(sum(parts) - ev.ms(0, nev - 1)) < 1e-2 + 1e-3 * ev.ms(0, nev - 1)
+    ev.close()
+    # too few events: an argument error
+    assert H.lib().hull_full_timed(ctypes.c_void_p(x.data_ptr()), n,
+                                   ctypes.c_void_p(faces.data_ptr()), 2 * n,
+                                   ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
+                                   wsb.numel(), sptr, ctypes.cast(ev.arr, ctypes.c_void_p),
+                                   nev - 1) == H.HULL_EINVAL
