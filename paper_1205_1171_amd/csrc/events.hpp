@@ -200,6 +200,8 @@ struct ParRun {
   int* segCnt;    // per segment: # bridge events
   int* segOff;    // exclusive scan of segCnt
   int2* segUV;    // per segment: the bridge at its start (found by the counting pass)
+  Event* segTmp;  // per segment: its first kSegKeep bridge events (counting pass)
+  int2* segTmpUV; // and the bridges after them
   Event* bev;     // bridge events of merge (s, e) at slots [2s, 2s + nB)
   int2* buv;      // (u, v) after each bridge event
   int* nB;        // per merge: # bridge events

@@ -567,6 +567,8 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.segCnt = (int*)(ws + pl.segCnt[r]);
     Q.segOff = (int*)(ws + pl.segOff[r]);
     Q.segUV = (int2*)(ws + pl.segUV[r]);
+    Q.segTmp = (Event*)(ws + pl.segTmp[r]);
+    Q.segTmpUV = (int2*)(ws + pl.segTmpUV[r]);
     Q.bev = (Event*)(ws + pl.bev[r]);
     Q.buv = (int2*)(ws + pl.buv[r]);
     Q.nB = (int*)(ws + pl.nB[r]);

@@ -157,7 +157,8 @@ __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
 // bridge in `uv0`.
 __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e, int seg,
                             int S, Event* out, int2* out_uv, int cap,
-                            int2* uv0, int2* start_uv, bool have_start) {
+                            int2* uv0, int2* start_uv, bool have_start, Event* keep = nullptr,
+                            int2* keep_uv = nullptr) {
   const int4* pts = R.pts;
   const int zs = R.zs;
   bool haveT = false, haveEnd = false;
@@ -292,6 +293,9 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
       }
       out[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind, T.st, 0.0};
       out_uv[nb] = make_int2(U.p, V.p);
+    } else if (keep && nb < kSegKeep) {
+      keep[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind, T.st, 0.0};
+      keep_uv[nb] = make_int2(U.p, V.p);
     }
     ++nb;
   }
@@ -535,13 +539,27 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
     }
     if (!write) {
       R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, 0,
-                                 i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], false);
+                                 i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], false,
+                                 R.segTmp + (int64_t)t * kSegKeep,
+                                 R.segTmpUV + (int64_t)t * kSegKeep);
       continue;
     }
     if (i == 0) R.nB[g] = R.segOff[first + S] - R.segOff[first];
-    if (R.segCnt[t] == 0) continue;  // nothing to write (the -inf bridge is known)
+    const int cnt = R.segCnt[t];
+    if (cnt == 0) continue;  // nothing to write (the -inf bridge is known)
     const int64_t off = R.segOff[t] - R.segOff[first];
     const int cap = (int)(2 * (e - s) - off);
+    if (cnt <= kSegKeep) {  // the counting pass kept them: copy
+      if (cnt > cap) {
+        atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
+        continue;
+      }
+      for (int q = 0; q < cnt; ++q) {
+        R.bev[2 * s + off + q] = R.segTmp[(int64_t)t * kSegKeep + q];
+        R.buv[2 * s + off + q] = R.segTmpUV[(int64_t)t * kSegKeep + q];
+      }
+      continue;
+    }
     walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.buv + 2 * s + off, cap, nullptr,
                  &R.segUV[t], true);
   }

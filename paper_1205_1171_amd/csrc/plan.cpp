@@ -80,6 +80,8 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.segCnt[r] = take((p.seg_cap + 1) * 4);
     p.segOff[r] = take((p.seg_cap + 1) * 4);
     p.segUV[r] = take((p.seg_cap + 1) * sizeof(int2));
+    p.segTmp[r] = take((p.seg_cap + 1) * kSegKeep * sizeof(Event));
+    p.segTmpUV[r] = take((p.seg_cap + 1) * kSegKeep * sizeof(int2));
     p.bev[r] = take(2 * nn * sizeof(Event));
     p.buv[r] = take(2 * nn * sizeof(int2));
     p.nB[r] = take((p.mcap + 1) * 4);
