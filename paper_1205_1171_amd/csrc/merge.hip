@@ -32,19 +32,15 @@
 
 namespace hull {
 
-__device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int64_t e) {
-  const int4* pts = R.pts;
-  int2* lk = R.lk;  // (pv, nx)
-  const int zs = R.zs;
-  const int nL = R.len_in[s], nR = R.len_in[m];
-  if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m)) {
-    atomicCAS(&h->err, 0, HULL_EINTERNAL);
-    R.len_out[s] = 0;
-    return;
-  }
-  const Event* Lev = R.ev_in + 2 * s;
-  const Event* Rev = R.ev_in + 2 * m;
-  Event* out = R.ev_out + 2 * s;
+// The merge of blocks [s, m) and [m, e) of the arrays pts and lk (working
+// links), whose index i holds the point of rank i + base: base = 0 for the
+// global arrays, the block start for a block staged in LDS.  Child events
+// (Lev, Rev), the merged movie (out) and the -inf link arrays (pv0, nx0) are
+// global and in global ranks.  Returns the merged movie's length, -1 after an
+// internal error.
+__device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, int* nx0, int base,
+                          const Event* Lev, int nL, const Event* Rev, int nR, Event* out,
+                          Header* h, int64_t s, int64_t m, int64_t e, int zs) {
   const int64_t cap = 2 * (e - s);
 
   // 1. bridge at t = -inf
@@ -53,11 +49,11 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   for (int guard = 0;; ++guard) {
     if (guard > 2 * (e - s) + 4) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
-      R.len_out[s] = 0;
-      return;
+      return -1;
     }
-    int w = R.nx0[v];
+    int w = nx0[v + base];
     if (w != kNil) {
+      w -= base;
       int4 Pw = pts[w];
       if (d_sign(Pu, Pv, Pw) < 0) {
         v = w;
@@ -65,8 +61,9 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
         continue;
       }
     }
-    w = R.pv0[u];
+    w = pv0[u + base];
     if (w != kNil) {
+      w -= base;
       int4 Pw = pts[w];
       if (d_sign(Pw, Pu, Pv) < 0) {
         u = w;
@@ -110,12 +107,20 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
   // the next event of each child, loaded one iteration ahead
   int4 EL = make_int4(0, 0, 0, 0), ER = make_int4(0, 0, 0, 0);
   double tL = 0.0, tR = 0.0;
+  // events hold global ranks: shifted to the arrays' indexing
+  const int4 shift = make_int4(base, base, base, 0);
   if (nL > 0) {
     EL = *(const int4*)&Lev[0];
+    EL.x -= shift.x;
+    EL.y -= shift.y;
+    EL.z -= shift.z;
     tL = Lev[0].t;
   }
   if (nR > 0) {
     ER = *(const int4*)&Rev[0];
+    ER.x -= shift.x;
+    ER.y -= shift.y;
+    ER.z -= shift.z;
     tR = Rev[0].t;
   }
   const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
@@ -224,11 +229,17 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
       if (bi == 0) {
         if (++i < nL) {
           EL = *(const int4*)&Lev[i];
+          EL.x -= shift.x;
+          EL.y -= shift.y;
+          EL.z -= shift.z;
           tL = Lev[i].t;
         }
       } else {
         if (++j < nR) {
           ER = *(const int4*)&Rev[j];
+          ER.x -= shift.x;
+          ER.y -= shift.y;
+          ER.z -= shift.z;
           tR = Rev[j].t;
         }
       }
@@ -267,14 +278,26 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      out[k] = Event{ba, bw, bb, bk, bs, 0.0};
+      out[k] = Event{ba + base, bw + base, bb + base, bk, bs, 0.0};
       ++k;
     }
   }
   // 3. splice the -inf chains
-  R.nx0[u0] = v0;
-  R.pv0[v0] = u0;
-  R.len_out[s] = k;
+  nx0[u0 + base] = v0 + base;
+  pv0[v0 + base] = u0 + base;
+  return k;
+}
+
+__device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int64_t e) {
+  const int nL = R.len_in[s], nR = R.len_in[m];
+  if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m)) {
+    atomicCAS(&h->err, 0, HULL_EINTERNAL);
+    R.len_out[s] = 0;
+    return;
+  }
+  const int k = merge_core(R.pts, R.lk, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+                           R.ev_out + 2 * s, h, s, m, e, R.zs);
+  R.len_out[s] = k < 0 ? 0 : k;
 }
 
 __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
@@ -290,6 +313,43 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
     return;
   }
   merge_one(R, A.h, s, m, e);
+}
+
+// The lowest levels with each lane's block (points and working links) staged
+// in LDS: the merge's scattered point and link accesses then stay on chip
+// (global memory serves only the sequential child events and the output).
+// One wavefront per workgroup; a lane touches only its own LDS slice.
+template <int W>
+__global__ void __launch_bounds__(64) k_merge_level_lds(LevelArgs A) {
+  __shared__ int4 sp[64 * W];
+  __shared__ int2 sl[64 * W];
+  const RunPtrs& R = A.run[blockIdx.y];
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (!R.pts || g >= A.S.moff[A.S.H]) return;
+  const int2 se = A.S.mlist[g];
+  const int64_t s = se.x, m = s + A.half, e = se.y;
+  if (A.h->err || e - s > W) {
+    if (!A.h->err) atomicCAS(&A.h->err, 0, HULL_EINTERNAL);
+    R.len_out[s] = 0;
+    return;
+  }
+  const int nL = R.len_in[s], nR = R.len_in[m];
+  if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m)) {
+    atomicCAS(&A.h->err, 0, HULL_EINTERNAL);
+    R.len_out[s] = 0;
+    return;
+  }
+  int4* P = sp + threadIdx.x * W;
+  int2* K = sl + threadIdx.x * W;
+  const int w = (int)(e - s), b = (int)s;
+  for (int j = 0; j < w; ++j) {
+    P[j] = R.pts[s + j];
+    const int pv = R.pv0[s + j], nx = R.nx0[s + j];
+    K[j] = make_int2(pv == kNil ? kNil : pv - b, nx == kNil ? kNil : nx - b);
+  }
+  const int k = merge_core(P, K, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+                           R.ev_out + 2 * s, A.h, 0, m - s, e - s, R.zs);
+  R.len_out[s] = k < 0 ? 0 : k;
 }
 
 // The unpaired trailing block of a hull at this level keeps its movie: copy
@@ -476,6 +536,9 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Lane-serial levels whose blocks (2, 4, 8 points) are staged in LDS.
+constexpr int kLdsLevels = 3;
+
 static int levels_for(int64_t n) {
   int L = 0;
   while ((int64_t(1) << L) < n) ++L;
@@ -610,11 +673,17 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       Q.len_in = R.len_in;
       Q.ev_out = R.ev_out;
       Q.len_out = R.len_out;
-      if (R.pts && serial)
+      if (R.pts && serial && k > kLdsLevels)
         hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.lk, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
-    if (serial) {
+    if (serial && k <= kLdsLevels) {
+      const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
+      const dim3 grid((unsigned)((bound + 63) / 64), 2);
+      if (k == 1) hipLaunchKernelGGL(k_merge_level_lds<2>, grid, dim3(64), 0, s, A);
+      else if (k == 2) hipLaunchKernelGGL(k_merge_level_lds<4>, grid, dim3(64), 0, s, A);
+      else hipLaunchKernelGGL(k_merge_level_lds<8>, grid, dim3(64), 0, s, A);
+    } else if (serial) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       hipLaunchKernelGGL(k_merge_level, dim3((unsigned)((bound + 255) / 256), 2), dim3(256), 0, s,
                          A);
