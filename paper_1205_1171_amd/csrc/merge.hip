@@ -536,8 +536,8 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Lane-serial levels whose blocks (2, 4, 8 points) are staged in LDS.
-constexpr int kLdsLevels = 3;
+// Lane-serial levels whose blocks (2, 4, 8, 16 points) are staged in LDS.
+constexpr int kLdsLevels = 4;
 
 static int levels_for(int64_t n) {
   int L = 0;
@@ -682,7 +682,8 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       const dim3 grid((unsigned)((bound + 63) / 64), 2);
       if (k == 1) hipLaunchKernelGGL(k_merge_level_lds<2>, grid, dim3(64), 0, s, A);
       else if (k == 2) hipLaunchKernelGGL(k_merge_level_lds<4>, grid, dim3(64), 0, s, A);
-      else hipLaunchKernelGGL(k_merge_level_lds<8>, grid, dim3(64), 0, s, A);
+      else if (k == 3) hipLaunchKernelGGL(k_merge_level_lds<8>, grid, dim3(64), 0, s, A);
+      else hipLaunchKernelGGL(k_merge_level_lds<16>, grid, dim3(64), 0, s, A);
     } else if (serial) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       hipLaunchKernelGGL(k_merge_level, dim3((unsigned)((bound + 255) / 256), 2), dim3(256), 0, s,
