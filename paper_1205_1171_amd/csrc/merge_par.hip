@@ -158,7 +158,7 @@ __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
 __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e, int seg,
                             int S, Event* out, int2* out_uv, int cap,
                             int2* uv0, int2* start_uv, bool have_start, Event* keep = nullptr,
-                            int2* keep_uv = nullptr) {
+                            int2* keep_uv = nullptr, const Event* resume = nullptr) {
   const int4* pts = R.pts;
   const int zs = R.zs;
   bool haveT = false, haveEnd = false;
@@ -174,6 +174,10 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
   if (seg + 1 < S) {
     Tend = cand_of(R.ev_in, boundary_slot(R, s, m, seg + 1, S));
     haveEnd = true;
+  }
+  if (resume) {  // continue after an event this segment already produced
+    T = cand_of(resume, 0);
+    haveT = true;
   }
   // the bridge at the start of the segment: walk to the lower common tangent
   // of the two chains, from the inner ends of the blocks (each step needs one
@@ -549,19 +553,22 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
     if (cnt == 0) continue;  // nothing to write (the -inf bridge is known)
     const int64_t off = R.segOff[t] - R.segOff[first];
     const int cap = (int)(2 * (e - s) - off);
-    if (cnt <= kSegKeep) {  // the counting pass kept them: copy
-      if (cnt > cap) {
-        atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
-        continue;
-      }
-      for (int q = 0; q < cnt; ++q) {
-        R.bev[2 * s + off + q] = R.segTmp[(int64_t)t * kSegKeep + q];
-        R.buv[2 * s + off + q] = R.segTmpUV[(int64_t)t * kSegKeep + q];
-      }
+    // the counting pass kept the first kSegKeep: copy them, and walk on from
+    // the last of them only for the rest
+    const int kept = cnt < kSegKeep ? cnt : kSegKeep;
+    if (cnt > cap) {
+      atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
       continue;
     }
-    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off, R.buv + 2 * s + off, cap, nullptr,
-                 &R.segUV[t], true);
+    for (int q = 0; q < kept; ++q) {
+      R.bev[2 * s + off + q] = R.segTmp[(int64_t)t * kSegKeep + q];
+      R.buv[2 * s + off + q] = R.segTmpUV[(int64_t)t * kSegKeep + q];
+    }
+    if (cnt <= kSegKeep) continue;
+    const int64_t last = (int64_t)t * kSegKeep + kSegKeep - 1;
+    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off + kSegKeep,
+                 R.buv + 2 * s + off + kSegKeep, cap - kSegKeep, nullptr, &R.segTmpUV[last],
+                 true, nullptr, nullptr, &R.segTmp[last]);
   }
 }
 
