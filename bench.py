@@ -6,8 +6,8 @@ level of the lower and upper runs, face extraction) on the n = 2^24 workload
 value = Mpoints/s = n / (time per step).
 
 Also reported on the same line:
-  roofline        the lane-serial merge kernel (k_merge_level, the largest
-                  share of the step): algorithmic bytes per launch (from the
+  roofline        the lane-serial merge kernel of levels 5-9 (k_merge_level,
+                  the largest share of the step): algorithmic bytes per launch (from the
                   oracle's per-level counters: 4 B per event read, 4 B per
                   event written, 28 B per point touched) over its average
                   launch time, measured with HIP events recorded around each
@@ -201,17 +201,21 @@ def single(args, hull, workloads):
     adj_ms = adjacency_ms(hull, faces[:F])
     roofline = levels = None
     S = min(sched.serial_levels, L)
+    KL = min(sched.fused_levels, S)  # lowest levels: the LDS-staged kernel
     if golden is not None:
         stats = np.array(golden["level_stats_lower"]) + np.array(golden["level_stats_upper"])
         Bk = 4.0 * stats[:, 0] + 4.0 * stats[:, 1] + 28.0 * stats[:, 2]  # bytes per level
-        levels = [{"level": k + 1, "kernel": "k_merge_level" if k < S else "parallel (13 kernels)",
+        levels = [{"level": k + 1,
+                   "kernel": ("k_merge_level_lds" if k < KL else "k_merge_level") if k < S
+                   else "parallel (13 kernels)",
                    "ms": round(float(lvl[k]), 4), "algorithmic_bytes": float(Bk[k]),
                    "GBps": round(float(Bk[k]) / (lvl[k] / 1e3) / 1e9, 2),
                    "frac": round(float(Bk[k]) / (lvl[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 6)}
                   for k in range(L)]
-        if S > 0:
-            per_launch = float(Bk[:S].sum()) / S
-            avg_ms = float(lvl[:S].mean())
+        if S > KL:
+            # k_merge_level: the lane-serial levels above the LDS-staged ones
+            per_launch = float(Bk[KL:S].sum()) / (S - KL)
+            avg_ms = float(lvl[KL:S].mean())
             achieved = per_launch / (avg_ms / 1e3) / 1e9
             traffic = None
             tpath = os.path.join(ROOT, "profiles", f"k_merge_level_{args.workload}_traffic.json")
@@ -220,12 +224,13 @@ def single(args, hull, workloads):
                 src = b"".join(open(os.path.join(ROOT, "paper_1205_1171_amd", "csrc", f), "rb").read()
                                for f in ("merge.hip", "events.hpp", "predicates.hpp"))
                 if (tr.get("source_sha256") == hashlib.sha256(src).hexdigest()
-                        and tr.get("serial_levels") == S):
+                        and tr.get("serial_levels") == S and tr.get("lds_levels") == KL):
                     traffic = tr.get("hbm_bytes_per_launch")
             roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                         "traffic": traffic, "kernel": "k_merge_level",
-                        "launches_per_step": S, "avg_launch_ms": round(avg_ms, 4),
+                        "levels": [KL + 1, S], "launches_per_step": S - KL,
+                        "avg_launch_ms": round(avg_ms, 4),
                         "algorithmic_bytes_per_launch": per_launch,
                         "all_levels_GBps": round(float(Bk.sum()) / (lvl.sum() / 1e3) / 1e9, 3)}
 

@@ -97,7 +97,8 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
  *                  paper's kernel, Sec. 3); the levels above split each merge
  *                  into time segments walked in parallel (default 9)
  *   walk_segment   child events per walk segment, >= 8 (default 8)
- *   fused_levels   reserved: pass 0 or -1
+ *   fused_levels   ignored on input (pass 0 or -1); hull_schedule_defaults
+ *                  writes the number of LDS-staged lowest levels here
  *   reserved       pass 0 */
 typedef struct hull_schedule_t {
   int32_t serial_levels;
@@ -108,8 +109,10 @@ typedef struct hull_schedule_t {
 
 /* The schedule the library uses when a call passes none (or leaves a field
  * at its default): the built-in defaults, overridden by the environment
- * variables HULL_SERIAL_LEVELS and HULL_WALK_SEGMENT when set.  Host,
- * synchronous. */
+ * variables HULL_SERIAL_LEVELS and HULL_WALK_SEGMENT when set.  On output,
+ * fused_levels is the number of lowest lane-serial levels that stage each
+ * merge's points and links in LDS (a separate kernel from the other
+ * lane-serial levels).  Host, synchronous. */
 int32_t hull_schedule_defaults(hull_schedule_t* out);
 
 /* Bytes of device workspace for hull_full_batched over H hulls of

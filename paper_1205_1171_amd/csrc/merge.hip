@@ -866,7 +866,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
   const hull::Opts o = hull::resolve(nullptr);
   out->serial_levels = o.serial_max;
   out->walk_segment = o.seg;
-  out->fused_levels = 0;
+  out->fused_levels = hull::kLdsLevels;
   out->reserved = 0;
   return HULL_OK;
 }

@@ -147,3 +147,20 @@ def test_delaunay_argument_errors(L):
     assert f(fake, -1, fake, 200, fake, fake, ws, None) == hull.HULL_EINVAL
     assert f(fake, 100, fake, 200, None, fake, ws, None) == hull.HULL_EINVAL
     assert f(fake, 100, fake, 200, fake, fake, ws - 1, None) == hull.HULL_EWORKSPACE
+
+
+def test_schedule_defaults(L, monkeypatch):
+    """Built-in defaults, the environment overrides, and the number of
+    LDS-staged levels reported in fused_levels."""
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
+        monkeypatch.delenv(k, raising=False)
+    s = hull.schedule_defaults()
+    assert (s.serial_levels, s.walk_segment) == (9, 8)
+    assert 0 <= s.fused_levels <= s.serial_levels and s.reserved == 0
+    monkeypatch.setenv("HULL_SERIAL_LEVELS", "12")
+    monkeypatch.setenv("HULL_WALK_SEGMENT", "32")
+    s = hull.schedule_defaults()
+    assert (s.serial_levels, s.walk_segment) == (12, 32)
+    monkeypatch.setenv("HULL_WALK_SEGMENT", "3")  # below the minimum of 8
+    assert hull.schedule_defaults().walk_segment == 8
+    assert L.hull_schedule_defaults(None) == hull.HULL_EINVAL
