@@ -52,7 +52,7 @@ struct Plan {
   size_t cntR[2], cntL[2], offR[2], offL[2], curR[2], curL[2], claimR[2], claimL[2];
   size_t entR[2], entL[2], ctr[2], touched[2];
   size_t ecnt[2], eoff[2], cslot[2], cmerge[2];
-  size_t segS[2], segBase[2], segMerge[2], segCnt[2], segOff[2], segUV[2];
+  size_t segS[2], segBase[2], segMerge[2], segB[2], segCnt[2], segOff[2], segUV[2];
   size_t segTmp[2], segTmpUV[2];  // the first kSegKeep bridge events of each segment
   size_t bev[2], buv[2], nB[2], boff[2], uv0[2], surv[2], jb[2], pre[2];
   size_t aR[2], aL[2], aT[2], wf[2];

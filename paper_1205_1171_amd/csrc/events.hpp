@@ -197,6 +197,7 @@ struct ParRun {
   int* segS;      // per merge: # time segments of its bridge walk
   int* segBase;   // exclusive scan of segS
   int* segMerge;  // per segment: its merge
+  int* segB;      // per segment: input-movie slot of the child event it starts after (-1: -inf)
   int* segCnt;    // per segment: # bridge events
   int* segOff;    // exclusive scan of segCnt
   int2* segUV;    // per segment: the bridge at its start (found by the counting pass)

@@ -627,6 +627,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.segS = (int*)(ws + pl.segS[r]);
     Q.segBase = (int*)(ws + pl.segBase[r]);
     Q.segMerge = (int*)(ws + pl.segMerge[r]);
+    Q.segB = (int*)(ws + pl.segB[r]);
     Q.segCnt = (int*)(ws + pl.segCnt[r]);
     Q.segOff = (int*)(ws + pl.segOff[r]);
     Q.segUV = (int2*)(ws + pl.segUV[r]);

@@ -135,14 +135,30 @@ __device__ int orient_after(const int4* pts, int a, int b, int c, const Cand& T,
 }
 
 // Segment i of S of a merge covers the events after boundary b_i up to and
-// including b_(i+1), b_0 = -inf, b_S = +inf; b_i (0 < i < S) is the event at
-// index floor(i * n / S) of the longer child movie.
-__device__ __forceinline__ int64_t boundary_slot(const ParRun& R, int64_t s, int64_t m, int i,
-                                                 int S) {
-  int nL = R.len_in[s], nR = R.len_in[m];
-  int64_t base = nL >= nR ? 2 * s : 2 * m;
-  int64_t nn = nL >= nR ? nL : nR;
-  return base + (int64_t)i * nn / S;
+// including b_(i+1), b_0 = -inf, b_S = +inf.  With N = nL + nR child events
+// in time order (both movies merged), b_i (0 < i < S) is the one at position
+// floor(i * N / S) - 1, so every segment spans the same number of child
+// events of the two movies together.  Found by a co-rank search: the number
+// jL of left-movie events among the first k = floor(i * N / S) is the first
+// j at which L[j] comes after R[k-1-j].  Returns b_i's input-movie slot.
+__device__ int64_t boundary_slot(const ParRun& R, int64_t s, int64_t m, int i, int S) {
+  const int nL = R.len_in[s], nR = R.len_in[m];
+  const int64_t N = (int64_t)nL + nR;
+  const int k = (int)((int64_t)i * N / S);
+  int lo = k - nR > 0 ? k - nR : 0, hi = k < nL ? k : nL;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (ev_cmp(R.pts, cand_of(R.ev_in, 2 * s + mid), cand_of(R.ev_in, 2 * m + (k - 1 - mid)),
+               R.zs) < 0)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  const int jL = lo, jR = k - lo;
+  if (jL == 0) return 2 * m + jR - 1;
+  if (jR == 0) return 2 * s + jL - 1;
+  const int64_t a = 2 * s + jL - 1, b = 2 * m + jR - 1;
+  return ev_cmp(R.pts, cand_of(R.ev_in, a), cand_of(R.ev_in, b), R.zs) > 0 ? a : b;
 }
 
 __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
@@ -155,8 +171,8 @@ __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
 // events in the segment; with `out` set, writes them there (and their
 // bridges after each move to `out_uv`).  Segment 0 also reports the -inf
 // bridge in `uv0`.
-__device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e, int seg,
-                            int S, Event* out, int2* out_uv, int cap,
+__device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e,
+                            int64_t b0, int64_t b1, Event* out, int2* out_uv, int cap,
                             int2* uv0, int2* start_uv, bool have_start, Event* keep = nullptr,
                             int2* keep_uv = nullptr, const Event* resume = nullptr) {
   const int4* pts = R.pts;
@@ -167,12 +183,12 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
   T.st = 0.0;
   T.kind = 0;
   Tend = T;
-  if (seg > 0) {
-    T = cand_of(R.ev_in, boundary_slot(R, s, m, seg, S));
+  if (b0 >= 0) {
+    T = cand_of(R.ev_in, b0);
     haveT = true;
   }
-  if (seg + 1 < S) {
-    Tend = cand_of(R.ev_in, boundary_slot(R, s, m, seg + 1, S));
+  if (b1 >= 0) {
+    Tend = cand_of(R.ev_in, b1);
     haveEnd = true;
   }
   if (resume) {  // continue after an event this segment already produced
@@ -510,11 +526,20 @@ __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
   }
 }
 
+// Per segment: its merge and the slot of the child event it starts after.
 __global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
   const int merges = R.ctr[4];
-  GRID_STRIDE(t, R.ctr[6]) R.segMerge[t] = find_owner(R.segBase, merges, t);
+  const int64_t half = int64_t(1) << (P.k - 1);
+  const bool err = P.h->err != 0;
+  GRID_STRIDE(t, R.ctr[6]) {
+    const int g = find_owner(R.segBase, merges, t);
+    R.segMerge[t] = g;
+    const int i = (int)(t - R.segBase[g]);
+    const int64_t s = P.S.mlist[g].x;
+    R.segB[t] = i == 0 || err ? -1 : (int)boundary_slot(R, s, s + half, i, R.segS[g]);
+  }
 }
 
 // Pass 1 counts each segment's bridge events; pass 2 writes them at their
@@ -533,6 +558,7 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
     const int first = R.segBase[g], S = R.segS[g], i = (int)(t - first);
     const int2 se = P.S.mlist[g];
     const int64_t s = se.x, m = s + half, e = se.y;
+    const int64_t b0 = R.segB[t], b1 = i + 1 < S ? R.segB[t + 1] : -1;
     if (P.h->err) {
       if (!write) R.segCnt[t] = 0;
       else if (i == 0) {
@@ -542,7 +568,7 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
       continue;
     }
     if (!write) {
-      R.segCnt[t] = walk_segment(R, P.h, s, m, e, i, S, nullptr, nullptr, 0,
+      R.segCnt[t] = walk_segment(R, P.h, s, m, e, b0, b1, nullptr, nullptr, 0,
                                  i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], false,
                                  R.segTmp + (int64_t)t * kSegKeep,
                                  R.segTmpUV + (int64_t)t * kSegKeep);
@@ -566,7 +592,7 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
     }
     if (cnt <= kSegKeep) continue;
     const int64_t last = (int64_t)t * kSegKeep + kSegKeep - 1;
-    walk_segment(R, P.h, s, m, e, i, S, R.bev + 2 * s + off + kSegKeep,
+    walk_segment(R, P.h, s, m, e, b0, b1, R.bev + 2 * s + off + kSegKeep,
                  R.buv + 2 * s + off + kSegKeep, cap - kSegKeep, nullptr, &R.segTmpUV[last],
                  true, nullptr, nullptr, &R.segTmp[last]);
   }

@@ -77,6 +77,7 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.segS[r] = take((p.mcap + 1) * 4);
     p.segBase[r] = take((p.mcap + 1) * 4);
     p.segMerge[r] = take((p.seg_cap + 1) * 4);
+    p.segB[r] = take((p.seg_cap + 1) * 4);
     p.segCnt[r] = take((p.seg_cap + 1) * 4);
     p.segOff[r] = take((p.seg_cap + 1) * 4);
     p.segUV[r] = take((p.seg_cap + 1) * sizeof(int2));
