@@ -20,7 +20,7 @@ constexpr int kBuckets = 1 << kRadixBits;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
 constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
-constexpr int kSegKeep = 4;  // bridge events a walk segment keeps from its counting pass
+constexpr int kSegKeep = 8;  // bridge events a walk segment keeps from its counting pass
 
 // Device-side status words at the head of every workspace.
 struct Header {
