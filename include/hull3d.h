@@ -96,7 +96,7 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
  *   serial_levels  merge levels 1..serial_levels run one lane per merge (the
  *                  paper's kernel, Sec. 3); the levels above split each merge
  *                  into time segments walked in parallel (default 9)
- *   walk_segment   child events per walk segment, >= 8 (default 8)
+ *   walk_segment   child events per walk segment, >= 4 (default 4)
  *   fused_levels   ignored on input (pass 0 or -1); hull_schedule_defaults
  *                  writes the number of LDS-staged lowest levels here
  *   reserved       pass 0 */

@@ -21,6 +21,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
 constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
 constexpr int kSegKeep = 8;  // bridge events a walk segment keeps from its counting pass
+constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
 
 // Device-side status words at the head of every workspace.
 struct Header {
@@ -63,7 +64,7 @@ struct Plan {
 };
 
 // min_seg: the smallest walk segment (child events) the plan must hold.
-Plan make_plan(int64_t n, int64_t H, int min_seg = 8);
+Plan make_plan(int64_t n, int64_t H, int min_seg = kMinWalkSegment);
 
 // The HIP error behind the last HULL_EHIP of this host thread.
 void note_hip_error(hipError_t e);

@@ -567,8 +567,8 @@ struct Opts {
 static Opts resolve(const hull_schedule_t* sc) {
   Opts o;
   o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 9);
-  o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 8);
-  if (o.seg < 8) o.seg = 8;
+  o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 4);
+  if (o.seg < kMinWalkSegment) o.seg = kMinWalkSegment;
   return o;
 }
 
@@ -858,7 +858,7 @@ const char* hull_strerror(int32_t code) {
 int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes) {
   (void)flags;
   if (!bytes || n < 0 || n > hull::kMaxN) return HULL_EINVAL;
-  *bytes = hull::make_plan(n, 1, 8).total;
+  *bytes = hull::make_plan(n, 1, hull::kMinWalkSegment).total;
   return HULL_OK;
 }
 
@@ -874,7 +874,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
 
 int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* bytes) {
   if (!bytes || total_points < 0 || total_points > hull::kMaxTotal || H < 1) return HULL_EINVAL;
-  *bytes = hull::make_plan(total_points, H, 8).total;
+  *bytes = hull::make_plan(total_points, H, hull::kMinWalkSegment).total;
   return HULL_OK;
 }
 

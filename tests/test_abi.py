@@ -155,12 +155,12 @@ def test_schedule_defaults(L, monkeypatch):
     for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
         monkeypatch.delenv(k, raising=False)
     s = hull.schedule_defaults()
-    assert (s.serial_levels, s.walk_segment) == (9, 8)
+    assert (s.serial_levels, s.walk_segment) == (9, 4)
     assert 0 <= s.fused_levels <= s.serial_levels and s.reserved == 0
     monkeypatch.setenv("HULL_SERIAL_LEVELS", "12")
     monkeypatch.setenv("HULL_WALK_SEGMENT", "32")
     s = hull.schedule_defaults()
     assert (s.serial_levels, s.walk_segment) == (12, 32)
-    monkeypatch.setenv("HULL_WALK_SEGMENT", "3")  # below the minimum of 8
-    assert hull.schedule_defaults().walk_segment == 8
+    monkeypatch.setenv("HULL_WALK_SEGMENT", "2")  # below the minimum of 4
+    assert hull.schedule_defaults().walk_segment == 4
     assert L.hull_schedule_defaults(None) == hull.HULL_EINVAL

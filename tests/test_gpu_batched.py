@@ -48,7 +48,7 @@ SCHEDULES = {
     "default": (-1, 0, -1),
     "serial": (99, 0, 0),
     "parallel": (0, 16, 0),
-    "parallel_seg8": (0, 8, 0),
+    "parallel_seg4": (0, 4, 0),
     "split3": (3, 32, 0),
 }
 

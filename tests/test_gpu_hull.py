@@ -43,12 +43,12 @@ def ws(H):
 # Merge strategies: every level lane-serial, every level parallel (bridge walk
 # and scatter), and the default split between them.  All must give the same
 # movies and faces.  The parallel strategy is also run with walk segments of
-# 8 child events, so that most walks start from a tangent found at a segment
+# 4 child events (the minimum), so that most walks start from a tangent found at a segment
 # boundary, and with a split after level 3.
 STRATEGIES = {
     "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": ""},
     "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16"},
-    "parallel_seg8": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "8"},
+    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4"},
     "split3_seg64": {"HULL_SERIAL_LEVELS": "3", "HULL_WALK_SEGMENT": "64"},
     "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": ""},
 }
