@@ -20,6 +20,7 @@ constexpr int kBuckets = 1 << kRadixBits;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
 constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
+constexpr int kScanDevGrid = 512;    // tile blocks per job of a device-length scan
 constexpr int kSegKeep = 8;  // bridge events a walk segment keeps from its counting pass
 constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
 

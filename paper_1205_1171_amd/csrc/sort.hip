@@ -298,15 +298,16 @@ __global__ void __launch_bounds__(kSortThreads)
     k_scan_tile_sums_dev(ScanJobs J, int add, int64_t cap, int64_t pstride, int32_t* partials) {
   const ScanJob& jb = J.j[blockIdx.y];
   const int64_t len = dev_len(jb.d_len, add, cap);
-  if ((int64_t)blockIdx.x * kScanBlock >= len) return;
   __shared__ int wsum[kSortThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  int s = 0;
-  for (int j = 0; j < kScanItems; ++j)
-    if (base + j < len) s += jb.in[base + j];
-  int total;
-  block_exclusive_scan(s, wsum, total);
-  if (threadIdx.x == 0) partials[blockIdx.y * pstride + blockIdx.x] = total;
+  for (int64_t tile = blockIdx.x; tile * kScanBlock < len; tile += gridDim.x) {
+    const int64_t base = tile * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    int s = 0;
+    for (int j = 0; j < kScanItems; ++j)
+      if (base + j < len) s += jb.in[base + j];
+    int total;
+    block_exclusive_scan(s, wsum, total);
+    if (threadIdx.x == 0) partials[blockIdx.y * pstride + tile] = total;
+  }
 }
 
 __global__ void __launch_bounds__(kSortThreads)
@@ -332,20 +333,21 @@ __global__ void __launch_bounds__(kSortThreads)
                      const int32_t* __restrict__ partials) {
   const ScanJob& jb = J.j[blockIdx.y];
   const int64_t len = dev_len(jb.d_len, add, cap);
-  if ((int64_t)blockIdx.x * kScanBlock >= len) return;
   __shared__ int wsum[kSortThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-  for (int j = 0; j < kScanItems; ++j) {
-    v[j] = base + j < len ? jb.in[base + j] : 0;
-    s += v[j];
-  }
-  int total;
-  int run = block_exclusive_scan(s, wsum, total) + partials[blockIdx.y * pstride + blockIdx.x];
-  for (int j = 0; j < kScanItems; ++j) {
-    if (base + j < len) jb.out[base + j] = run;
-    run += v[j];
+  for (int64_t tile = blockIdx.x; tile * kScanBlock < len; tile += gridDim.x) {
+    const int64_t base = tile * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = base + j < len ? jb.in[base + j] : 0;
+      s += v[j];
+    }
+    int total;
+    int run = block_exclusive_scan(s, wsum, total) + partials[blockIdx.y * pstride + tile];
+    for (int j = 0; j < kScanItems; ++j) {
+      if (base + j < len) jb.out[base + j] = run;
+      run += v[j];
+    }
   }
 }
 
@@ -355,12 +357,15 @@ int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_
   if (J.count > kMaxScanJobs) return HULL_EINVAL;
   const int64_t blocks = (cap + kScanBlock - 1) / kScanBlock;
   const int64_t pstride = blocks + 1;
-  hipLaunchKernelGGL(k_scan_tile_sums_dev, dim3((unsigned)blocks, J.count), dim3(kSortThreads), 0,
-                     s, J, add, cap, pstride, partials);
+  // the lengths are known only on the device: a capped grid strides over
+  // the tiles, so a short scan under a large cap launches few idle blocks
+  const unsigned grid = (unsigned)(blocks < kScanDevGrid ? blocks : kScanDevGrid);
+  hipLaunchKernelGGL(k_scan_tile_sums_dev, dim3(grid, J.count), dim3(kSortThreads), 0, s, J, add,
+                     cap, pstride, partials);
   hipLaunchKernelGGL(k_scan_sums_dev, dim3(J.count), dim3(kSortThreads), 0, s, J, add, cap,
                      pstride, partials);
-  hipLaunchKernelGGL(k_scan_tiles_dev, dim3((unsigned)blocks, J.count), dim3(kSortThreads), 0, s,
-                     J, add, cap, pstride, partials);
+  hipLaunchKernelGGL(k_scan_tiles_dev, dim3(grid, J.count), dim3(kSortThreads), 0, s, J, add, cap,
+                     pstride, partials);
   HULL_LAUNCH_CHECK();
   return HULL_OK;
 }
