@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned_schedules.json")
 
 SERIAL_LEVELS = (7, 8, 9, 10, 11, 12, 13, 14, 99)
-WALK_SEGMENTS = (8, 16, 32)
+WALK_SEGMENTS = (4, 8, 16, 32)
 
 
 def shape_key(offsets):
