@@ -23,6 +23,7 @@ constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
 constexpr int kScanDevGrid = 512;    // tile blocks per job of a device-length scan
 constexpr int kSegKeep = 8;  // bridge events a walk segment keeps from its counting pass
 constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
+constexpr int kWorkBins = 1024;     // child-event counts told apart when ordering merges
 
 // Device-side status words at the head of every workspace.
 struct Header {
@@ -50,6 +51,7 @@ struct Plan {
   size_t ev[2][2], len[2][2];  // [run][buffer]
   // the level schedule (merge list, trailing blocks)
   size_t mcnt, moff, tcnt, toff, tlist, mlist;
+  size_t perm[2], wbins[2];  // per run: merges in work order, work histogram
   // parallel merge strategy, per run
   size_t cntR[2], cntL[2], offR[2], offL[2], curR[2], curL[2], claimR[2], claimL[2];
   size_t entR[2], entL[2], ctr[2], touched[2];

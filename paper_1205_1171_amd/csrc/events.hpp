@@ -39,6 +39,8 @@ struct Sched {
 
 struct LevelArgs {
   RunPtrs run[2];
+  int* perm[2];   // per run: merge of each lane (nullptr: lane g takes merge g)
+  int* wbins[2];  // per run: histogram, then cursors, of the work order
   Header* h;
   Sched S;
   int64_t n;

@@ -301,9 +301,11 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
 }
 
 __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const RunPtrs& R = A.run[blockIdx.y];
-  if (!R.pts || g >= A.S.moff[A.S.H]) return;
+  if (!R.pts || t >= A.S.moff[A.S.H]) return;
+  const int* perm = A.perm[blockIdx.y];
+  const int64_t g = perm ? perm[t] : t;
   const int2 se = A.S.mlist[g];
   const int64_t s = se.x, m = s + A.half, e = se.y;
   // After an error the movies are empty, so that every later kernel still
@@ -313,6 +315,91 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
     return;
   }
   merge_one(R, A.h, s, m, e);
+}
+
+// Lane-serial levels from this one on list their merges in work order; below
+// it the merge kernel moves about as many bytes as the memory system serves
+// (L2 misses), and the order would only add its own launches.
+constexpr int kOrderFromLevel = 6;
+
+// Work order of a level's merges.  The lanes of a wavefront run their merges
+// in lockstep, so a wave lasts as long as its longest merge; listing the
+// merges by child event count, largest first, gives each wave merges of
+// about the same length (and starts the longest first).  A counting sort:
+// histogram, scan, placement; the order inside a count is arbitrary and
+// changes nothing but timing (every merge writes only its own block).
+__device__ __forceinline__ int work_bin(const LevelArgs& A, const RunPtrs& R, int64_t g) {
+  const int64_t s = A.S.mlist[g].x;
+  int w = R.len_in[s] + R.len_in[s + A.half];
+  w = w < 0 ? 0 : (w > kWorkBins - 1 ? kWorkBins - 1 : w);
+  return kWorkBins - 1 - w;
+}
+
+__global__ void __launch_bounds__(256) k_work_clear(LevelArgs A) {
+  if (!A.run[blockIdx.y].pts) return;
+  for (int i = threadIdx.x; i < kWorkBins; i += blockDim.x) A.wbins[blockIdx.y][i] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_work_hist(LevelArgs A) {
+  __shared__ int hist[kWorkBins];
+  const RunPtrs& R = A.run[blockIdx.y];
+  const int64_t M = A.S.moff[A.S.H];
+  if (!R.pts || blockIdx.x * (int64_t)blockDim.x >= M) return;
+  for (int i = threadIdx.x; i < kWorkBins; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < M) atomicAdd(&hist[work_bin(A, R, g)], 1);
+  __syncthreads();
+  int* bins = A.wbins[blockIdx.y];
+  for (int i = threadIdx.x; i < kWorkBins; i += blockDim.x)
+    if (hist[i]) atomicAdd(&bins[i], hist[i]);
+}
+
+// One wavefront per run: the histogram becomes each bin's first position.
+__global__ void __launch_bounds__(64) k_work_scan(LevelArgs A) {
+  if (!A.run[blockIdx.y].pts) return;
+  int* bins = A.wbins[blockIdx.y];
+  constexpr int per = kWorkBins / 64;
+  int v[per];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    v[j] = bins[threadIdx.x * per + j];
+    sum += v[j];
+  }
+  int incl = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if ((int)threadIdx.x >= o) incl += y;
+  }
+  int run = incl - sum;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    bins[threadIdx.x * per + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_work_place(LevelArgs A) {
+  __shared__ int cnt[kWorkBins];
+  __shared__ int base[kWorkBins];
+  const RunPtrs& R = A.run[blockIdx.y];
+  const int64_t M = A.S.moff[A.S.H];
+  if (!R.pts || blockIdx.x * (int64_t)blockDim.x >= M) return;
+  for (int i = threadIdx.x; i < kWorkBins; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int b = -1, local = 0;
+  if (g < M) {
+    b = work_bin(A, R, g);
+    local = atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  int* cur = A.wbins[blockIdx.y];
+  for (int i = threadIdx.x; i < kWorkBins; i += blockDim.x)
+    base[i] = cnt[i] ? atomicAdd(&cur[i], cnt[i]) : 0;
+  __syncthreads();
+  if (b >= 0) A.perm[blockIdx.y][base[b] + local] = (int)g;
 }
 
 // The lowest levels with each lane's block (points and working links) staged
@@ -687,8 +774,19 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       else hipLaunchKernelGGL(k_merge_level_lds<16>, grid, dim3(64), 0, s, A);
     } else if (serial) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
-      hipLaunchKernelGGL(k_merge_level, dim3((unsigned)((bound + 255) / 256), 2), dim3(256), 0, s,
-                         A);
+      const dim3 grid((unsigned)((bound + 255) / 256), 2);
+      LevelArgs B = A;
+      if (k >= kOrderFromLevel) {
+        for (int r = 0; r < 2; ++r) {
+          B.perm[r] = (int*)(ws + pl.perm[r]);
+          B.wbins[r] = (int*)(ws + pl.wbins[r]);
+        }
+        hipLaunchKernelGGL(k_work_clear, dim3(1, 2), dim3(256), 0, s, B);
+        hipLaunchKernelGGL(k_work_hist, grid, dim3(256), 0, s, B);
+        hipLaunchKernelGGL(k_work_scan, dim3(1, 2), dim3(64), 0, s, B);
+        hipLaunchKernelGGL(k_work_place, grid, dim3(256), 0, s, B);
+      }
+      hipLaunchKernelGGL(k_merge_level, grid, dim3(256), 0, s, B);
     } else {
       P.k = k;
       P.run[0].stamp = P.run[1].stamp = k;

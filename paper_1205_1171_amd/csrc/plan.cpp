@@ -49,6 +49,10 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
   p.toff = take((hh + 1) * 4);
   p.tlist = take(hh * 4);
   p.mlist = take(p.mcap * sizeof(int2));
+  for (int r = 0; r < 2; ++r) {
+    p.perm[r] = take(p.mcap * 4);
+    p.wbins[r] = take(kWorkBins * 4);
+  }
   p.fcnt = take((hh + 1) * 4);
   for (int r = 0; r < 2; ++r) {
     p.pv0[r] = take(nn * 4);
