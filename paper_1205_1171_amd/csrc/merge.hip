@@ -319,8 +319,13 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
 
 // Lane-serial levels from this one on list their merges in work order; below
 // it the merge kernel moves about as many bytes as the memory system serves
-// (L2 misses), and the order would only add its own launches.
+// (L2 misses), and the order would only add its own launches.  A level with
+// fewer merges than one wave per SIMD (256 CUs x 4 SIMDs x 64 lanes over two
+// runs) keeps the plain order: with the waves already spread one to a SIMD,
+// packing the longest merges into one wave only adds up their divergent
+// branches.
 constexpr int kOrderFromLevel = 6;
+constexpr int64_t kOrderMinMerges = 32768;
 
 // Work order of a level's merges.  The lanes of a wavefront run their merges
 // in lockstep, so a wave lasts as long as its longest merge; listing the
@@ -776,7 +781,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 255) / 256), 2);
       LevelArgs B = A;
-      if (k >= kOrderFromLevel) {
+      if (k >= kOrderFromLevel && bound >= kOrderMinMerges) {
         for (int r = 0; r < 2; ++r) {
           B.perm[r] = (int*)(ws + pl.perm[r]);
           B.wbins[r] = (int*)(ws + pl.wbins[r]);
