@@ -189,8 +189,11 @@ typedef struct {
     int64_t touched;
 } run_t;
 
+/* Per-level accounting: a point counts once per level when a merge of that
+   level reads its coordinates (a predicate) or changes its links (act, the
+   -inf splice, the rewind). */
 static void touch(run_t* R, int32_t p) {
-    if (R->stamp && R->stamp[p] != R->stamp_now) {
+    if (p != NIL && R->stamp && R->stamp[p] != R->stamp_now) {
         R->stamp[p] = R->stamp_now;
         R->touched++;
     }
@@ -270,6 +273,7 @@ static int ev_cmp(const event_t* A, const event_t* B) {
 static void act(run_t* R, int32_t p) {
     int32_t* prev = R->prev;
     int32_t* next = R->next;
+    touch(R, p); touch(R, prev[p]); touch(R, next[p]);
     if (next[prev[p]] != p) {
         next[prev[p]] = p;
         prev[next[p]] = p;
@@ -329,6 +333,7 @@ static int64_t merge(run_t* R, int32_t m, const int32_t* Lmov, int64_t nL,
 
     /* Go back in time, restoring the merged -inf chain and leaving every
        off-chain point pointing at the neighbours of its insertion. */
+    touch(R, u); touch(R, v);
     next[u] = v;
     prev[v] = u;
     for (int64_t q = k - 1; q >= 0; --q) {
@@ -338,6 +343,7 @@ static int64_t merge(run_t* R, int32_t m, const int32_t* Lmov, int64_t nL,
             if (w == u) u = prev[u];
             else if (w == v) v = next[v];
         } else {
+            touch(R, w); touch(R, u); touch(R, v);
             next[u] = w; prev[w] = u;
             prev[v] = w; next[w] = v;
             if (w < m) u = w; else v = w;
