@@ -15,7 +15,14 @@ the cloud).
 For the Delaunay workload (planar: 2^18 points in [-2^14, 2^14]^2) it
 records the SHA-256 of the oracle's canonical triangle array.
 
-usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3 cfg4 planar
+For the differentiation workload cfg5 (256 clouds of 16,384 float32 points,
+hulls on their int32 lattice points) it records, per cloud, the oracle's face
+count, the SHA-256 of the concatenated canonical face arrays, the FP64 volume
+and area of each cloud (float64 positions of the float32 points, the oracle's
+faces), and the FP64 gradient of a seeded weighted loss sum_b wV[b] V_b +
+wA[b] A_b at 16 seeded vertices of every cloud.
+
+usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3 cfg4 cfg5 planar
 (the lower and upper runs go to two processes; the clouds of cfg4 to a pool)
 """
 import hashlib
@@ -91,6 +98,62 @@ def make_batched(name, workers):
     print(name, rec["F"], rec["oracle_seconds_cpu"], rec["oracle_seconds_wall"], flush=True)
 
 
+CFG5_GRAD_SEED = 12051175
+CFG5_GRAD_VERTS = 16
+
+
+def _cloud5(args):
+    from oracle import volume_area as va
+    P32, Pi, b, wV, wA, seed = args
+    t = time.time()
+    f = oracle.hull(Pi)
+    P64 = P32.astype(np.float64)
+    V, A = va.volume_area(P64, f)
+    gV, gA = va.gradients(P64, f)
+    rng = np.random.default_rng([seed, b])
+    verts = rng.choice(np.unique(f), CFG5_GRAD_VERTS, replace=False)
+    g = wV * gV[verts] + wA * gA[verts]
+    return validate.canonical(f).astype("<i4"), V, A, verts, g, time.time() - t
+
+
+def make_cfg5(name, workers):
+    P, Pi = workloads.cfg5()
+    B = len(P)
+    wrng = np.random.default_rng(CFG5_GRAD_SEED)
+    wV = wrng.standard_normal(B)
+    wA = wrng.standard_normal(B)
+    t = time.time()
+    jobs = [(P[b], Pi[b], b, float(wV[b]), float(wA[b]), CFG5_GRAD_SEED) for b in range(B)]
+    with ProcessPoolExecutor(workers) as ex:
+        res = list(ex.map(_cloud5, jobs, chunksize=2))
+    sha = hashlib.sha256()
+    for r in res:
+        sha.update(r[0].tobytes())
+    rec = {
+        "config": name,
+        "B": int(B),
+        "m": int(P.shape[1]),
+        "input_sha256": hashlib.sha256(np.ascontiguousarray(Pi, dtype="<i4").tobytes()).hexdigest(),
+        "positions_sha256": hashlib.sha256(np.ascontiguousarray(P, dtype="<f4").tobytes()).hexdigest(),
+        "F": int(sum(len(r[0]) for r in res)),
+        "F_per_cloud": [int(len(r[0])) for r in res],
+        "sha256_full": sha.hexdigest(),
+        "V64": [float(r[1]) for r in res],
+        "A64": [float(r[2]) for r in res],
+        "grad_seed": CFG5_GRAD_SEED,
+        "grad_wV": [float(x) for x in wV],
+        "grad_wA": [float(x) for x in wA],
+        "grad_vertices": [[int(v) for v in r[3]] for r in res],
+        "grad64": [[[float(x) for x in row] for row in r[4]] for r in res],
+        "oracle_seconds_cpu": float(sum(r[5] for r in res)),
+        "oracle_seconds_wall": time.time() - t,
+        "oracle_workers": workers,
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(rec, fh)
+    print(name, rec["F"], rec["oracle_seconds_cpu"], rec["oracle_seconds_wall"], flush=True)
+
+
 def make_delaunay(name):
     """The Delaunay workload: the oracle's lifted lower hull, CCW triangles."""
     from oracle import delaunay as dl
@@ -115,6 +178,8 @@ def make(name):
         return make_delaunay(name)
     if name == "cfg4":
         return make_batched(name, int(os.environ.get("GOLDEN_WORKERS", "6")))
+    if name == "cfg5":
+        return make_cfg5(name, int(os.environ.get("GOLDEN_WORKERS", "6")))
     p = MAKERS[name]()
     with ProcessPoolExecutor(2) as ex:
         res = sorted(ex.map(_run, [(name, 0), (name, 1)]), key=lambda r: r[0])

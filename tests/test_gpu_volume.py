@@ -5,6 +5,10 @@ Bars: forward |V32 - V64| / |V64| <= 1e-5 (same for A); gradient
 ||G32 - G||_F / ||G||_F <= 1e-4 per cloud against the FP64 analytic gradient
 and against central differences on sampled coordinates.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -122,3 +126,62 @@ def test_degenerate_zero_area_faces():
     assert np.linalg.norm(G - (gV + gA)) <= 1e-5 * np.linalg.norm(gV + gA)
     V64, A64 = va.volume_area(P[0].astype(np.float64), f)
     assert abs(V.item() - V64) <= 1e-5 * V64 and abs(A.item() - A64) <= 1e-5 * A64
+
+
+def test_cfg5_full_size():
+    """The differentiation workload at its stated size (256 clouds of 16,384
+    points): faces from one batched hull call in the benchmark's schedule
+    against the oracle's stored digest; V and A of every cloud against the
+    stored FP64 values; the gradient of the stored weighted loss against the
+    stored FP64 values at sampled vertices, against the FP64 analytic
+    gradient of every cloud, and against central differences on four clouds."""
+    import torch
+    from paper_1205_1171_amd import autotune, hull
+    from paper_1205_1171_amd.autograd import volume_area
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg5.json")
+    rec = json.load(open(path))
+    P, Pi = workloads.cfg5()
+    B, m = P.shape[0], P.shape[1]
+    assert hashlib.sha256(np.ascontiguousarray(Pi, dtype="<i4").tobytes()).hexdigest() == \
+        rec["input_sha256"]
+    off = np.arange(0, B * m + 1, m, dtype=np.int64)
+    x = torch.from_numpy(np.ascontiguousarray(Pi.reshape(-1, 3))).cuda()
+    say("cfg5 batched hull", B, m)
+    faces, face_off = hull.hull_batched_sync(x, off, schedule=autotune.lookup(off))
+    f = faces.cpu().numpy()
+    fo = face_off.cpu().numpy()
+    assert np.diff(fo).tolist() == rec["F_per_cloud"]
+    sha = hashlib.sha256()
+    for b in range(B):
+        sha.update(validate.canonical(f[fo[b]:fo[b + 1]]).astype("<i4").tobytes())
+    assert sha.hexdigest() == rec["sha256_full"]
+    say("cfg5 forward/backward")
+    p = torch.from_numpy(P.reshape(-1, 3).copy()).cuda().requires_grad_(True)
+    pt_off = torch.from_numpy(off).cuda()
+    V, A = volume_area(p, pt_off, faces.contiguous(), face_off)
+    wV = torch.tensor(rec["grad_wV"], dtype=torch.float32, device="cuda")
+    wA = torch.tensor(rec["grad_wA"], dtype=torch.float32, device="cuda")
+    ((V * wV).sum() + (A * wA).sum()).backward()
+    V, A = V.detach().cpu().numpy(), A.detach().cpu().numpy()
+    G = p.grad.cpu().numpy().reshape(B, m, 3)
+    V64, A64 = np.array(rec["V64"]), np.array(rec["A64"])
+    assert (np.abs(V - V64) <= 1e-5 * np.abs(V64)).all()
+    assert (np.abs(A - A64) <= 1e-5 * np.abs(A64)).all()
+    wv, wa = np.array(rec["grad_wV"]), np.array(rec["grad_wA"])
+    rng = np.random.default_rng(55)
+    for b in range(B):
+        g64 = np.array(rec["grad64"][b])
+        g32 = G[b, rec["grad_vertices"][b]]
+        assert np.linalg.norm(g32 - g64) <= 1e-4 * np.linalg.norm(g64), b
+        fb = f[fo[b]:fo[b + 1]]
+        P64 = P[b].astype(np.float64)
+        gV, gA = va.gradients(P64, fb)
+        Gb = wv[b] * gV + wa[b] * gA
+        assert np.linalg.norm(G[b] - Gb) <= 1e-4 * np.linalg.norm(Gb), b
+        if b % 64 == 0:
+            verts = np.unique(fb)
+            coords = [(int(v), k) for v in rng.choice(verts, 64, replace=False) for k in range(3)]
+            fd = va.finite_difference(P64, fb, coords, h=1.0)
+            gfd = wv[b] * fd[:, 0] + wa[b] * fd[:, 1]
+            g32 = np.array([G[b, i, k] for i, k in coords])
+            assert np.linalg.norm(g32 - gfd) <= 1e-4 * np.linalg.norm(gfd), b
