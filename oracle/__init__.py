@@ -18,6 +18,9 @@ Modules
 ``volume_area``   FP64 hull volume and area and their gradients.
 ``adjacency``     face adjacency (half-edge twins) of a face list.
 ``delaunay``      2-d Delaunay by lifting, and the in-circle pin.
+``floatin``       float input: the snap to an integer lattice with a
+                  power-of-two scale, then the exact hull (wide range).
+``kinetic_py``    a second merge in Python that recounts the level counters.
 """
 import ctypes
 import os
@@ -53,8 +56,9 @@ def _load():
     lib.oracle_level_movies.argtypes = [P, i64, i32, i32, P, i64, P, P]
     lib.oracle_level_chains.argtypes = [P, i64, i32, i32, P, P]
     lib.oracle_predicate.argtypes = [P, i32, i32]
+    lib.oracle_hull_wide.argtypes = [P, i64, i32, P, i64, P]
     for f in (lib.oracle_sort, lib.oracle_hull, lib.oracle_level_movies,
-              lib.oracle_level_chains, lib.oracle_predicate):
+              lib.oracle_level_chains, lib.oracle_predicate, lib.oracle_hull_wide):
         f.restype = i32
     _lib = lib
     return lib
@@ -107,6 +111,22 @@ def hull(xyz, lower_only=False, upper_only=False, topdown=False, stats=False):
         raise OracleError(rc)
     f = faces[: nf.value].copy()
     return (f, st) if stats else f
+
+
+def hull_wide(xyz, lower_only=False, upper_only=False, topdown=False):
+    """hull() on int64 rows over the wide range |x|, |y| <= 2^30, |z| <= 2^42
+    (the same method, predicates and perturbation)."""
+    a = np.ascontiguousarray(np.asarray(xyz, dtype=np.int64).reshape(-1, 3))
+    n = a.shape[0]
+    flags = (1 if lower_only else 0) | (2 if topdown else 0) | (4 if upper_only else 0)
+    cap = max(2 * n, 1)
+    faces = np.empty((cap, 3), dtype=np.int32)
+    nf = ctypes.c_int64(0)
+    rc = _load().oracle_hull_wide(a.ctypes.data, n, flags, faces.ctypes.data, cap,
+                                  ctypes.addressof(nf))
+    if rc:
+        raise OracleError(rc)
+    return faces[: nf.value].copy()
 
 
 def level_movies(xyz, run, level):

@@ -134,3 +134,26 @@ def block_movie(P, I, ranks, run):
         ev.append((tau, (int(ranks[l]), int(ranks[m]), int(ranks[r])), ins))
     ev.sort(key=lambda e: (e[0], e[1]))
     return np.array([[*e[1], e[2]] for e in ev], dtype=np.int64).reshape(-1, 4)
+
+
+def hull_faces_exact(P, I=None):
+    """hull_faces for any coordinate size (tiny n): every orientation is the
+    textbook determinant of points moved by concrete tiny epsilons, in exact
+    big integers (``perturb``)."""
+    P = [[int(v) for v in r] for r in np.asarray(P).reshape(-1, 3)]
+    n = len(P)
+    I = list(range(n)) if I is None else [int(i) for i in I]
+    if n < 3:
+        return np.zeros((0, 3), dtype=np.int64)
+    if n == 3:
+        return np.array([[0, 1, 2], [0, 2, 1]], dtype=np.int64)
+    K = perturb.choose_k(max(abs(v) for r in P for v in r), max(I))
+    pz = perturb.Perturbed(P, I, K)
+    out = []
+    for a, b, c in combinations(range(n), 3):
+        sg = [perturb.sign(pz.orient3d(a, b, c, d)) for d in range(n) if d not in (a, b, c)]
+        if all(v < 0 for v in sg):
+            out.append((a, b, c))
+        elif all(v > 0 for v in sg):
+            out.append((a, c, b))
+    return np.array(out, dtype=np.int64).reshape(-1, 3)

@@ -1,24 +1,31 @@
 """2-d Delaunay triangulation by lifting (test infrastructure): the lower
-hull of (x, y, x^2 + y^2) under the oracle's perturbed exact hull, each
-lower face turned counter-clockwise in the plane.  Plus the checks that pin
+hull of (x, y, x^2 + y^2) under the oracle's perturbed exact hull (its wide
+range: |x|, |y| <= 2^20, lifted z <= 2^41), each lower face turned
+counter-clockwise in the plane.  Plus the checks that pin
 it: the exact in-circle test and the triangle count."""
 import numpy as np
 
-from . import hull as _hull
+from . import hull_wide as _hull_wide
+
+
+MAX_XY = 1 << 20  # lifted z = x^2 + y^2 <= 2^41: the oracle's wide range
 
 
 def lift(xy):
     xy = np.asarray(xy, dtype=np.int64).reshape(-1, 2)
     z = xy[:, 0] * xy[:, 0] + xy[:, 1] * xy[:, 1]
-    return np.ascontiguousarray(np.column_stack([xy, z]).astype(np.int32))
+    return np.ascontiguousarray(np.column_stack([xy, z]))
 
 
 def delaunay(xy):
-    """Triangles [T, 3] of input indices, counter-clockwise."""
+    """Triangles [T, 3] of input indices, counter-clockwise (|x|, |y| <=
+    2^20)."""
     xy = np.asarray(xy).reshape(-1, 2)
+    if np.abs(xy).max(initial=0) > MAX_XY:
+        raise ValueError("|x|, |y| must be at most 2^20")
     if len(xy) < 3:
         return np.zeros((0, 3), dtype=np.int32)
-    f = _hull(lift(xy), lower_only=True)
+    f = _hull_wide(lift(xy), lower_only=True)
     return np.ascontiguousarray(f[:, [0, 2, 1]]).astype(np.int32)
 
 

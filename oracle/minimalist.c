@@ -40,6 +40,11 @@
 #define NIL (-1)
 #define ORACLE_MAX_N (1LL << 26)
 #define ORACLE_MAX_COORD (1LL << 29)
+/* The wide entry (float-lattice and lifted inputs): |x|, |y| <= 2^30,
+   |z| <= 2^42.  The largest product then formed, a coefficient of
+   N_A * D_B, stays below 2^200. */
+#define ORACLE_MAX_XY_WIDE (1LL << 30)
+#define ORACLE_MAX_Z_WIDE (1LL << 42)
 
 /* ------------------------------------------------------------------------ */
 /* Signed 256-bit integers, two's complement, four 64-bit limbs.            */
@@ -102,8 +107,9 @@ static i256 big_mul(i256 a, i256 b) {
         }
         prod[i + 4] = (uint64_t)carry;
     }
-    /* Every product formed here is bounded far below 2^255 (|coord| <= 2^29,
-       index < 2^26); anything larger is a bug, not an input error. */
+    /* Every product formed here is bounded far below 2^255 (|x|, |y| <= 2^30,
+       |z| <= 2^42, index < 2^26); anything larger is a bug, not an input
+       error. */
     if (prod[4] | prod[5] | prod[6] | prod[7] | (prod[3] >> 63)) abort();
     i256 r;
     for (int k = 0; k < 4; ++k) r.w[k] = prod[k];
@@ -428,10 +434,10 @@ static int32_t* hull_bottomup(run_t* R, int32_t* A, int32_t* B, int64_t* lenA, i
 /* ------------------------------------------------------------------------ */
 /* Setup: rank order by (x, input index).                                   */
 /* ------------------------------------------------------------------------ */
-static const int32_t* g_sort_xyz;
+static const int64_t* g_sort_xyz;
 static int cmp_rank(const void* pa, const void* pb) {
     int32_t a = *(const int32_t*)pa, b = *(const int32_t*)pb;
-    int32_t xa = g_sort_xyz[3 * (int64_t)a], xb = g_sort_xyz[3 * (int64_t)b];
+    int64_t xa = g_sort_xyz[3 * (int64_t)a], xb = g_sort_xyz[3 * (int64_t)b];
     if (xa != xb) return xa < xb ? -1 : 1;
     return a < b ? -1 : (a > b);
 }
@@ -443,6 +449,17 @@ static int check_input(const int32_t* xyz, int64_t n) {
     return 0;
 }
 
+static int check_input_wide(const int64_t* xyz, int64_t n) {
+    if (n < 0 || n > ORACLE_MAX_N || (n > 0 && !xyz)) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        if (xyz[3 * k] > ORACLE_MAX_XY_WIDE || xyz[3 * k] < -ORACLE_MAX_XY_WIDE ||
+            xyz[3 * k + 1] > ORACLE_MAX_XY_WIDE || xyz[3 * k + 1] < -ORACLE_MAX_XY_WIDE ||
+            xyz[3 * k + 2] > ORACLE_MAX_Z_WIDE || xyz[3 * k + 2] < -ORACLE_MAX_Z_WIDE)
+            return -3;
+    }
+    return 0;
+}
+
 typedef struct {
     run_t R;
     int32_t* order; /* rank -> input index */
@@ -450,7 +467,7 @@ typedef struct {
     int64_t *lenA, *lenB;
 } ctx_t;
 
-static int ctx_init(ctx_t* C, const int32_t* xyz, int64_t n) {
+static int ctx_init(ctx_t* C, const int64_t* xyz, int64_t n) {
     memset(C, 0, sizeof(*C));
     int64_t nn = n > 0 ? n : 1;
     C->order = malloc(sizeof(int32_t) * nn);
@@ -489,6 +506,16 @@ static void ctx_free(ctx_t* C) {
     free(C->A); free(C->B); free(C->lenA); free(C->lenB);
 }
 
+/* ctx_init on int32 rows (widened to int64 first). */
+static int ctx_init32(ctx_t* C, const int32_t* xyz, int64_t n) {
+    int64_t* w = malloc(sizeof(int64_t) * 3 * (n > 0 ? n : 1));
+    if (!w) { memset(C, 0, sizeof(*C)); return -4; }
+    for (int64_t k = 0; k < 3 * n; ++k) w[k] = xyz[k];
+    int rc = ctx_init(C, w, n);
+    free(w);
+    return rc;
+}
+
 /* Replay one block's movie from its -inf state: for each event w emit its
    face (prev(w), w, next(w)) and whether it is an insertion, then act(w).
    The links are restored afterwards by undoing the events in reverse. */
@@ -513,9 +540,45 @@ int32_t oracle_sort(const int32_t* xyz, int64_t n, int32_t* out) {
     int rc = check_input(xyz, n);
     if (rc) return rc;
     ctx_t C;
-    if (ctx_init(&C, xyz, n)) { ctx_free(&C); return -4; }
+    if (ctx_init32(&C, xyz, n)) { ctx_free(&C); return -4; }
     memcpy(out, C.order, sizeof(int32_t) * (size_t)n);
     ctx_free(&C);
+    return 0;
+}
+
+static int32_t hull_of_ctx(ctx_t* C, int64_t n, int32_t flags, int32_t* faces,
+                           int64_t* nfaces, int64_t* level_stats, int32_t max_levels) {
+    int64_t F = 0;
+    for (int run = 0; run < 2; ++run) {
+        if (run == 0 && (flags & 4)) continue;
+        if (run == 1 && (flags & 1)) continue;
+        C->R.zsign = run == 0 ? 1 : -1;
+        int32_t* mov;
+        int64_t len;
+        if (flags & 2) {
+            len = hull_topdown(&C->R, 0, (int32_t)n, C->A, C->B);
+            mov = C->A;
+        } else {
+            stats_t st = {level_stats ? level_stats + (int64_t)4 * max_levels * run : NULL, max_levels};
+            int64_t* lf;
+            for (int64_t p = 0; p < n; ++p) C->R.stamp[p] = 0;
+            mov = hull_bottomup(&C->R, C->A, C->B, C->lenA, C->lenB, -1, &st, &lf);
+            len = lf[0];
+        }
+        /* Output: replay from -inf, orient each face outward. */
+        for (int64_t q = 0; q < len; ++q) {
+            int32_t w = mov[q], a = C->R.prev[w], b = C->R.next[w];
+            int ds = D_sign(&C->R, a, w, b);
+            int keep = run == 0 ? ds < 0 : ds > 0; /* lower: normal z < 0 */
+            int32_t p0 = a, p1 = keep ? w : b, p2 = keep ? b : w;
+            faces[3 * F + 0] = C->order[p0];
+            faces[3 * F + 1] = C->order[p1];
+            faces[3 * F + 2] = C->order[p2];
+            F++;
+            act(&C->R, w);
+        }
+    }
+    *nfaces = F;
     return 0;
 }
 
@@ -533,38 +596,25 @@ int32_t oracle_hull(const int32_t* xyz, int64_t n, int32_t flags, int32_t* faces
     *nfaces = 0;
     if (n < 3) return 0;
     ctx_t C;
+    if (ctx_init32(&C, xyz, n)) { ctx_free(&C); return -4; }
+    hull_of_ctx(&C, n, flags, faces, nfaces, level_stats, max_levels);
+    ctx_free(&C);
+    return 0;
+}
+
+/* oracle_hull on int64 rows over the wider range |x|, |y| <= 2^30,
+   |z| <= 2^42 (lattice points of float inputs, lifted planar points); the
+   same method and predicates, the same perturbation by input index. */
+int32_t oracle_hull_wide(const int64_t* xyz, int64_t n, int32_t flags, int32_t* faces,
+                         int64_t cap, int64_t* nfaces) {
+    int rc = check_input_wide(xyz, n);
+    if (rc) return rc;
+    if (!faces || !nfaces || cap < 2 * n) return -1;
+    *nfaces = 0;
+    if (n < 3) return 0;
+    ctx_t C;
     if (ctx_init(&C, xyz, n)) { ctx_free(&C); return -4; }
-    int64_t F = 0;
-    for (int run = 0; run < 2; ++run) {
-        if (run == 0 && (flags & 4)) continue;
-        if (run == 1 && (flags & 1)) continue;
-        C.R.zsign = run == 0 ? 1 : -1;
-        int32_t* mov;
-        int64_t len;
-        if (flags & 2) {
-            len = hull_topdown(&C.R, 0, (int32_t)n, C.A, C.B);
-            mov = C.A;
-        } else {
-            stats_t st = {level_stats ? level_stats + (int64_t)4 * max_levels * run : NULL, max_levels};
-            int64_t* lf;
-            for (int64_t p = 0; p < n; ++p) C.R.stamp[p] = 0;
-            mov = hull_bottomup(&C.R, C.A, C.B, C.lenA, C.lenB, -1, &st, &lf);
-            len = lf[0];
-        }
-        /* Output: replay from -inf, orient each face outward. */
-        for (int64_t q = 0; q < len; ++q) {
-            int32_t w = mov[q], a = C.R.prev[w], b = C.R.next[w];
-            int ds = D_sign(&C.R, a, w, b);
-            int keep = run == 0 ? ds < 0 : ds > 0; /* lower: normal z < 0 */
-            int32_t p0 = a, p1 = keep ? w : b, p2 = keep ? b : w;
-            faces[3 * F + 0] = C.order[p0];
-            faces[3 * F + 1] = C.order[p1];
-            faces[3 * F + 2] = C.order[p2];
-            F++;
-            act(&C.R, w);
-        }
-    }
-    *nfaces = F;
+    hull_of_ctx(&C, n, flags, faces, nfaces, NULL, 0);
     ctx_free(&C);
     return 0;
 }
@@ -580,7 +630,7 @@ int32_t oracle_level_movies(const int32_t* xyz, int64_t n, int32_t run, int32_t 
     *total = 0;
     if (n < 1) return 0;
     ctx_t C;
-    if (ctx_init(&C, xyz, n)) { ctx_free(&C); return -4; }
+    if (ctx_init32(&C, xyz, n)) { ctx_free(&C); return -4; }
     C.R.zsign = run == 0 ? 1 : -1;
     int64_t* lf;
     int32_t* mov = hull_bottomup(&C.R, C.A, C.B, C.lenA, C.lenB, level, NULL, &lf);
@@ -606,7 +656,7 @@ int32_t oracle_level_chains(const int32_t* xyz, int64_t n, int32_t run, int32_t 
     if (rc) return rc;
     if (n < 1) return 0;
     ctx_t C;
-    if (ctx_init(&C, xyz, n)) { ctx_free(&C); return -4; }
+    if (ctx_init32(&C, xyz, n)) { ctx_free(&C); return -4; }
     C.R.zsign = run == 0 ? 1 : -1;
     int64_t* lf;
     hull_bottomup(&C.R, C.A, C.B, C.lenA, C.lenB, level, NULL, &lf);

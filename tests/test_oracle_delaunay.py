@@ -64,3 +64,47 @@ def test_degenerate_grid():
         for d in range(len(P)):
             if d not in (a, b, c):
                 assert dl.incircle(P, P[a], P[b], P[c], P[d]) <= 0
+
+
+def test_full_range_general_position():
+    """|x|, |y| up to 2^20 (lifted z up to 2^41): empty circles by the exact
+    in-circle test, and Qhull's triangulation."""
+    import scipy.spatial
+    rng = np.random.default_rng(10)
+    for t in range(3):
+        p = general_position(rng, 40, 1 << 20)
+        tris = dl.delaunay(p)
+        assert all(o > 0 for o in dl.orient(p, tris))
+        P = [tuple(int(v) for v in q) for q in p]
+        for a, b, c in tris:
+            for d in range(len(P)):
+                if d not in (a, b, c):
+                    assert dl.incircle(P, P[a], P[b], P[c], P[d]) <= 0
+        assert len(tris) == 2 * len(p) - hull_vertex_count(p) - 2
+    p = general_position(rng, 2000, 1 << 20)
+    ours = validate.canonical(dl.delaunay(p))
+    q = scipy.spatial.Delaunay(p.astype(np.float64)).simplices
+    q = np.array([s if dl.orient(p, [s])[0] > 0 else s[[0, 2, 1]] for s in q])
+    assert (ours == validate.canonical(q)).all()
+
+
+def test_full_range_degenerate_grid():
+    """The cocircular grid moved to the corner of the range: the same
+    properties as at the origin (the split of each square may differ: the
+    lifting turns a translation into a shear of z, which the perturbation of
+    z does not follow, so only properties are compared)."""
+    g = np.array([(x, y) for x in range(7) for y in range(6)], dtype=np.int64)
+    g = g + np.array([(1 << 20) - 6, -(1 << 20)])
+    tris = dl.delaunay(g)
+    areas = dl.orient(g, tris)
+    assert all(a >= 0 for a in areas) and sum(areas) == 2 * 6 * 5
+    assert sum(1 for a in areas if a > 0) == 2 * 6 * 5
+    P = [tuple(int(v) for v in q) for q in g]
+    for (a, b, c), ar in zip(tris, areas):
+        if ar == 0:
+            continue
+        for d in range(len(P)):
+            if d not in (a, b, c):
+                assert dl.incircle(P, P[a], P[b], P[c], P[d]) <= 0
+    with pytest.raises(ValueError):
+        dl.delaunay(np.array([[0, 0], [1, 0], [(1 << 20) + 1, 5]]))
