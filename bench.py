@@ -542,6 +542,7 @@ def differentiation(hull, workloads, autotune, reps):
     V, A = hull.volume_area_fwd(p, d_off, faces, face_off)
     ok = bool(torch.isfinite(V).all() and torch.isfinite(A).all() and (V > 0).all())
     log(f"fwd+bwd batched {ms_b:.3f} ms, per cloud {ms_c:.3f} ms")
+    check = diff_check(hull, p, d_off, faces, face_off, V, A, B, m)
     return {
         "workload": f"cfg5: {B} clouds x {m} points on a sphere of radius 2^18 with radial "
                     f"noise sigma 2^10, FP32",
@@ -552,7 +553,44 @@ def differentiation(hull, workloads, autotune, reps):
         "ms_hull_fwd_bwd_one_launch_per_cloud": round(ms_hc, 3),
         "speedup_with_hull": round(ms_hc / ms_hb, 2),
         "finite_positive_volumes": ok,
+        **check,
     }
+
+
+def diff_check(hull, p, d_off, faces, face_off, V, A, B, m):
+    """The differentiation workload's results against the oracle's stored
+    values: the canonical face digest of all clouds, V and A of every cloud
+    (FP64), and the gradient of the stored weighted loss at the stored
+    sampled vertices (FP64)."""
+    import numpy as np
+    import torch
+    from oracle import validate
+    gpath = os.path.join(ROOT, "tests", "golden", "cfg5.json")
+    if not os.path.exists(gpath):
+        return {"bit_exact": None}
+    rec = json.load(open(gpath))
+    f = faces.cpu().numpy()
+    fo = face_off.cpu().numpy()
+    sha = hashlib.sha256()
+    for b in range(B):
+        sha.update(validate.canonical(f[fo[b]:fo[b + 1]]).astype("<i4").tobytes())
+    exact = np.diff(fo).tolist() == rec["F_per_cloud"] and sha.hexdigest() == rec["sha256_full"]
+    V, A = V.cpu().numpy().astype(np.float64), A.cpu().numpy().astype(np.float64)
+    V64, A64 = np.array(rec["V64"]), np.array(rec["A64"])
+    wV = torch.tensor(rec["grad_wV"], dtype=torch.float32, device="cuda")
+    wA = torch.tensor(rec["grad_wA"], dtype=torch.float32, device="cuda")
+    G = hull.volume_area_bwd(p, d_off, faces, face_off, wV, wA)
+    G = G.cpu().numpy().reshape(B, m, 3).astype(np.float64)
+    gerr = 0.0
+    for b in range(B):
+        g64 = np.array(rec["grad64"][b])
+        g32 = G[b, rec["grad_vertices"][b]]
+        gerr = max(gerr, float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)))
+    return {"bit_exact": bool(exact),
+            "max_rel_err_V": float(np.max(np.abs(V - V64) / np.abs(V64))),
+            "max_rel_err_A": float(np.max(np.abs(A - A64) / np.abs(A64))),
+            "max_rel_err_grad": gerr,
+            "tolerances": {"V": 1e-5, "A": 1e-5, "grad": 1e-4}}
 
 
 def main():

@@ -201,6 +201,8 @@ int32_t hull_adjacency_workspace_bytes(int64_t F, size_t* bytes);
  *              edge used twice, not a 2-manifold) and the number of edges
  *              without a twin (0 for a closed surface)
  *   d_ws       workspace of hull_adjacency_workspace_bytes(F) bytes
+ * F may be at most (2^31 - 3) / 3 (half-edge ids 3f + k are int32); larger F
+ * returns HULL_EINVAL here and from hull_adjacency_workspace_bytes.
  * A hash table of directed edges in the workspace: one insertion pass, one
  * lookup pass (deterministic result). */
 int32_t hull_face_adjacency(const int32_t* d_faces, int64_t F, const int64_t* d_face_off,

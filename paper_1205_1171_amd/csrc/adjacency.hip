@@ -17,6 +17,8 @@
 namespace hull {
 
 constexpr unsigned long long kEmptyKey = ~0ull;
+// Half-edge ids 3f + k are stored as int32: at most this many faces.
+constexpr int64_t kMaxAdjFaces = (int64_t(INT32_MAX) - 2) / 3;
 
 struct __align__(16) EdgeSlot {
   unsigned long long key;
@@ -151,7 +153,7 @@ static size_t adj_ws_bytes(int64_t F) { return 256 + (size_t(1) << table_bits(F)
 extern "C" {
 
 int32_t hull_adjacency_workspace_bytes(int64_t F, size_t* bytes) {
-  if (!bytes || F < 0 || F > (int64_t(1) << 30)) return HULL_EINVAL;
+  if (!bytes || F < 0 || F > hull::kMaxAdjFaces) return HULL_EINVAL;
   *bytes = hull::adj_ws_bytes(F);
   return HULL_OK;
 }
@@ -159,7 +161,7 @@ int32_t hull_adjacency_workspace_bytes(int64_t F, size_t* bytes) {
 int32_t hull_face_adjacency(const int32_t* d_faces, int64_t F, const int64_t* d_face_off,
                             const int64_t* d_pt_off, int64_t H, int32_t* d_adj, int64_t* d_info,
                             void* d_ws, size_t ws_bytes, void* stream) {
-  if (F < 0 || F > (int64_t(1) << 30) || !d_info || !d_ws || (F > 0 && (!d_faces || !d_adj)) ||
+  if (F < 0 || F > hull::kMaxAdjFaces || !d_info || !d_ws || (F > 0 && (!d_faces || !d_adj)) ||
       (d_face_off && (!d_pt_off || H < 1)) || (!d_face_off && d_pt_off))
     return HULL_EINVAL;
   if (ws_bytes < hull::adj_ws_bytes(F)) return HULL_EWORKSPACE;

@@ -25,6 +25,15 @@ constexpr int kSegKeep = 8;  // bridge events a walk segment keeps from its coun
 constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
 constexpr int kWorkBins = 1024;     // child-event counts told apart when ordering merges
 
+// Slots of the per-run counter region of the parallel merge strategy.
+constexpr int kCtrTouched = 2;   // per-point link-change lists allocated this level
+constexpr int kCtrMerges = 4;    // merges of the level
+constexpr int kCtrEvents = 5;    // child events of the level
+constexpr int kCtrSegments = 6;  // walk segments of the level
+constexpr int kCtrBridge = 7;    // bridge events of the level
+constexpr int kCtrSlots = 8;     // size of the region (int32 words)
+static_assert(kCtrBridge < kCtrSlots, "counter region too small");
+
 // Device-side status words at the head of every workspace.
 struct Header {
   int32_t err;      // first error seen on the device (HULL_* code), 0 = none

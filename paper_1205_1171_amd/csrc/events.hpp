@@ -189,7 +189,7 @@ struct ParRun {
   int stamp;      // this level's claim stamp: lists of other points are empty
   Event* entR;    // link-change events grouped by point, time-sorted (kind | slot << 1)
   Event* entL;
-  int* ctr;       // [2] touched lists; [4..7] level totals: merges, child events,
+  int* ctr;       // [kCtrSlots]: touched lists; level totals of merges, child events,
                   // walk segments, bridge events
   int* touched;   // (point << 1 | side) of every allocated list
   int* ecnt;      // per merge: child events (mcap + 1)

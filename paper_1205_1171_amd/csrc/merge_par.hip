@@ -334,8 +334,8 @@ __global__ void __launch_bounds__(256) k_par_prep(ParLevel P) {
   const int64_t half = int64_t(1) << (P.k - 1);
   GRID_STRIDE(g, (int64_t)merges + 1) {
     if (g == 0) {
-      R.ctr[2] = 0;
-      R.ctr[4] = merges;
+      R.ctr[kCtrTouched] = 0;
+      R.ctr[kCtrMerges] = merges;
     }
     if (g < merges && !P.h->err) {
       const int2 se = P.S.mlist[g];
@@ -354,15 +354,15 @@ __global__ void __launch_bounds__(256) k_par_prep(ParLevel P) {
 __global__ void k_par_totals(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts || threadIdx.x) return;
-  const int merges = R.ctr[4];
-  R.ctr[5] = R.eoff[merges];
-  R.ctr[6] = R.segBase[merges];
+  const int merges = R.ctr[kCtrMerges];
+  R.ctr[kCtrEvents] = R.eoff[merges];
+  R.ctr[kCtrSegments] = R.segBase[merges];
 }
 
 __global__ void k_par_btotal(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts || threadIdx.x) return;
-  R.ctr[7] = R.boff[R.ctr[4]];
+  R.ctr[kCtrBridge] = R.boff[R.ctr[kCtrMerges]];
 }
 
 // The compact list of child events (slot and merge of each), and the
@@ -370,7 +370,7 @@ __global__ void k_par_btotal(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_enum(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int merges = R.ctr[4], E = R.ctr[5];
+  const int merges = R.ctr[kCtrMerges], E = R.ctr[kCtrEvents];
   const int64_t half = int64_t(1) << (P.k - 1);
   GRID_STRIDE(c, E) {
     const int g = find_owner(R.eoff, merges, c);
@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(256) k_par_enum(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  GRID_STRIDE(c, R.ctr[5]) {
+  GRID_STRIDE(c, R.ctr[kCtrEvents]) {
     const Event X = R.ev_in[R.cslot[c]];
     atomicAdd(&R.cntR[X.a], 1);
     atomicAdd(&R.cntL[X.b], 1);
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_claim(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int E = R.ctr[5], st = R.stamp;
+  const int E = R.ctr[kCtrEvents], st = R.stamp;
   GRID_STRIDE(c, (int64_t)E + 1) {
     if (c == E) {  // the scans read one entry past the last event
       R.aR[c] = R.aL[c] = R.aT[c] = 0;
@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(256) k_par_claim(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int E = R.ctr[5];
+  const int E = R.ctr[kCtrEvents];
   // capacities: 4n entries per side (at most 2 per child event, 2n events),
   // 2n touched lists (one per point and side)
   const int64_t ent_cap = 2 * (int64_t)P.ecap, touched_cap = P.ecap;
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
   }
   GRID_STRIDE(c, (int64_t)E + 1) {
     if (c == E) {
-      R.ctr[2] = R.aT[E];  // touched lists of the level
+      R.ctr[kCtrTouched] = R.aT[E];  // touched lists of the level
       continue;
     }
     const unsigned bits = R.wf[c];
@@ -499,7 +499,7 @@ __global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts || P.h->err) return;  // after an error the offsets may be stale
-  GRID_STRIDE(c, R.ctr[5]) {
+  GRID_STRIDE(c, R.ctr[kCtrEvents]) {
     const int q = R.cslot[c];
     const Event E = R.ev_in[q];
     const Event X{E.a, E.w, E.b, (q << 1) | E.kind, E.t, 0.0};
@@ -519,7 +519,7 @@ __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts || P.h->err) return;
-  GRID_STRIDE(t, R.ctr[2]) {
+  GRID_STRIDE(t, R.ctr[kCtrTouched]) {
     const int x = R.touched[t], p = x >> 1;
     if (x & 1) sort_entries(R.entL + R.offL[p], R.cntL[p]);
     else sort_entries(R.entR + R.offR[p], R.cntR[p]);
@@ -530,10 +530,10 @@ __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
 __global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int merges = R.ctr[4];
+  const int merges = R.ctr[kCtrMerges];
   const int64_t half = int64_t(1) << (P.k - 1);
   const bool err = P.h->err != 0;
-  GRID_STRIDE(t, R.ctr[6]) {
+  GRID_STRIDE(t, R.ctr[kCtrSegments]) {
     const int g = find_owner(R.segBase, merges, t);
     R.segMerge[t] = g;
     const int i = (int)(t - R.segBase[g]);
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
 __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int total = R.ctr[6];
+  const int total = R.ctr[kCtrSegments];
   const int64_t half = int64_t(1) << (P.k - 1);
   GRID_STRIDE(t, (int64_t)total + 1) {
     if (t == total) {  // the scan reads one entry past the last segment
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
 __global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int E = R.ctr[5];
+  const int E = R.ctr[kCtrEvents];
   const int64_t half = int64_t(1) << (P.k - 1);
   const bool err = P.h->err != 0;
   GRID_STRIDE(c, (int64_t)E + 1) {
@@ -629,7 +629,7 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
   const bool err = P.h->err != 0;
-  const int merges = R.ctr[4], E = R.ctr[5], Bt = R.ctr[7];
+  const int merges = R.ctr[kCtrMerges], E = R.ctr[kCtrEvents], Bt = R.ctr[kCtrBridge];
   const int64_t half = int64_t(1) << (P.k - 1);
   GRID_STRIDE(t, (int64_t)E + Bt + merges) {
     if (t < E) {
@@ -719,14 +719,14 @@ int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   const dim3 g2(kStrideBlocks, 2), b256(256);
   hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
   // per merge: child events, walk segments (length: merges + 1)
-  int32_t rc = exclusive_scan_dev_multi(jobs_of(P, {0, 1}, 4), 1, P.S.mcap + 1, partials, s);
+  int32_t rc = exclusive_scan_dev_multi(jobs_of(P, {0, 1}, kCtrMerges), 1, P.S.mcap + 1, partials, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_totals, dim3(1, 2), dim3(64), 0, s, P);
   hipLaunchKernelGGL(k_par_enum, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_count, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_claim, g2, b256, 0, s, P);
   // per child event: list entries and lists it allocates (length: events + 1)
-  rc = exclusive_scan_dev_multi(jobs_of(P, {2, 3, 4}, 5), 1, P.ecap + 1, partials, s);
+  rc = exclusive_scan_dev_multi(jobs_of(P, {2, 3, 4}, kCtrEvents), 1, P.ecap + 1, partials, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_place, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_fill, g2, b256, 0, s, P);
@@ -734,14 +734,14 @@ int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_par_segtable, g2, b256, 0, s, P);
   const dim3 gw(16384, 2), b64(64);
   hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 0);
-  rc = exclusive_scan_dev_multi(jobs_of(P, {5}, 6), 1, P.seg_cap + 1, partials, s);
+  rc = exclusive_scan_dev_multi(jobs_of(P, {5}, kCtrSegments), 1, P.seg_cap + 1, partials, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 1);
-  rc = exclusive_scan_dev_multi(jobs_of(P, {6}, 4), 1, P.S.mcap + 1, partials, s);
+  rc = exclusive_scan_dev_multi(jobs_of(P, {6}, kCtrMerges), 1, P.S.mcap + 1, partials, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_btotal, dim3(1, 2), dim3(64), 0, s, P);
   hipLaunchKernelGGL(k_par_classify, g2, b256, 0, s, P);
-  rc = exclusive_scan_dev_multi(jobs_of(P, {7}, 5), 1, P.ecap + 1, partials, s);
+  rc = exclusive_scan_dev_multi(jobs_of(P, {7}, kCtrEvents), 1, P.ecap + 1, partials, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_scatter, g2, b256, 0, s, P);
   HULL_LAUNCH_CHECK();

@@ -72,7 +72,7 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.claimL[r] = take(nn * 4);
     p.entR[r] = take(4 * nn * sizeof(Event));
     p.entL[r] = take(4 * nn * sizeof(Event));
-    p.ctr[r] = take(4 * sizeof(int32_t));
+    p.ctr[r] = take(kCtrSlots * sizeof(int32_t));
     p.touched[r] = take(2 * nn * 4);
     p.ecnt[r] = take((p.mcap + 1) * 4);
     p.eoff[r] = take((p.mcap + 1) * 4);

@@ -135,6 +135,16 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Context that makes ``stream`` current (no-op for None), so that the
+    temporaries a wrapper allocates and the copies it makes are ordered on
+    the stream its kernels run on (the caching allocator then also keeps
+    them until that stream is done with them)."""
+    import contextlib
+    import torch
+    return contextlib.nullcontext() if stream is None else torch.cuda.stream(stream)
+
+
 def _check_points(xyz):
     import torch
     if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.int32):
@@ -162,8 +172,13 @@ def hull(xyz, lower_only=False, ws=None, faces=None, info=None, stream=None):
 
     Asynchronous: the first info[1] rows of ``faces`` are valid once the
     stream reaches this point.  Use :func:`hull_sync` for a checked result."""
-    import torch
     _check_points(xyz)
+    with _on(stream):
+        return _hull(xyz, lower_only, ws, faces, info)
+
+
+def _hull(xyz, lower_only, ws, faces, info):
+    import torch
     n = xyz.shape[0]
     dev = xyz.device
     cap = max(2 * n, 1)
@@ -176,7 +191,7 @@ def hull(xyz, lower_only=False, ws=None, faces=None, info=None, stream=None):
     fn = lib().hull_lower if lower_only else lib().hull_full
     rc = fn(ctypes.c_void_p(xyz.data_ptr()), n, ctypes.c_void_p(faces.data_ptr()), faces.shape[0],
             ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(),
-            _stream(stream))
+            _stream(None))
     if rc:
         raise HullError(rc, "hull_lower" if lower_only else "hull_full")
     return faces, info
@@ -197,8 +212,13 @@ def hull_batched(xyz, offsets, schedule=None, ws=None, faces=None, stream=None):
     info [2]) on the device; the faces of cloud h are rows
     [face_offsets[h], face_offsets[h+1]), indices local to the cloud.
     Asynchronous, like :func:`hull`."""
-    import torch
     _check_points(xyz)
+    with _on(stream):
+        return _hull_batched(xyz, offsets, schedule, ws, faces)
+
+
+def _hull_batched(xyz, offsets, schedule, ws, faces):
+    import torch
     h_off = torch.as_tensor(offsets, dtype=torch.int64).cpu().contiguous()
     H = h_off.numel() - 1
     if H < 1 or int(h_off[-1]) != xyz.shape[0]:
@@ -218,7 +238,7 @@ def hull_batched(xyz, offsets, schedule=None, ws=None, faces=None, stream=None):
                                  ctypes.c_void_p(faces.data_ptr()), faces.shape[0],
                                  ctypes.c_void_p(face_off.data_ptr()),
                                  ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()),
-                                 wbuf.numel(), sc, _stream(stream))
+                                 wbuf.numel(), sc, _stream(None))
     if rc:
         raise HullError(rc, "hull_full_batched")
     return faces, face_off, info
@@ -321,9 +341,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _check_volume_args(p, pt_off, faces, face_off):
+    import torch
+    for name, t, dt in (("p", p, torch.float32), ("pt_off", pt_off, torch.int64),
+                        ("faces", faces, torch.int32), ("face_off", face_off, torch.int64)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous CUDA {dt} tensor")
+        if t.device != p.device:
+            raise ValueError(f"{name} is on {t.device}, points on {p.device}")
+    if p.dim() != 2 or p.shape[1] != 3 or faces.dim() != 2 or faces.shape[1] != 3:
+        raise ValueError("p and faces must be [N, 3] and [F, 3]")
+    if pt_off.dim() != 1 or face_off.shape != pt_off.shape or pt_off.numel() < 2:
+        raise ValueError("pt_off and face_off must both be [H + 1], H >= 1")
+
+
 def volume_area_fwd(p, pt_off, faces, face_off, stream=None):
     """(V, A) per cloud, float32 device tensors [H]."""
     import torch
+    _check_volume_args(p, pt_off, faces, face_off)
     H = pt_off.numel() - 1
     V = torch.empty(H, dtype=torch.float32, device=p.device)
     A = torch.empty(H, dtype=torch.float32, device=p.device)
@@ -335,9 +370,17 @@ def volume_area_fwd(p, pt_off, faces, face_off, stream=None):
 
 
 def volume_area_bwd(p, pt_off, faces, face_off, gV, gA, stream=None):
-    """Gradient [N, 3] of sum(gV * V + gA * A) with respect to p."""
+    """Gradient [N, 3] of sum(gV * V + gA * A) with respect to p (gV or gA
+    may be None)."""
     import torch
+    _check_volume_args(p, pt_off, faces, face_off)
     H = pt_off.numel() - 1
+    for name, t in (("gV", gV), ("gA", gA)):  # None: that term has no gradient
+        if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda
+                                  and t.dtype == torch.float32 and t.is_contiguous()
+                                  and t.numel() == H and t.device == p.device):
+            raise TypeError(f"{name} must be None or a contiguous CUDA float32 tensor of {H} "
+                            "entries")
     g = torch.empty_like(p)
     rc = lib().hull_volume_area_bwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
                                     _ptr(gV), _ptr(gA), _ptr(g), _stream(stream))

@@ -164,3 +164,15 @@ def test_schedule_defaults(L, monkeypatch):
     monkeypatch.setenv("HULL_WALK_SEGMENT", "2")  # below the minimum of 4
     assert hull.schedule_defaults().walk_segment == 4
     assert L.hull_schedule_defaults(None) == hull.HULL_EINVAL
+
+
+def test_adjacency_face_limit(L):
+    """Half-edge ids are int32: F above (2^31 - 3) / 3 is refused."""
+    out = ctypes.c_size_t(0)
+    fmax = ((1 << 31) - 3) // 3
+    assert L.hull_adjacency_workspace_bytes(fmax, ctypes.byref(out)) == hull.HULL_OK
+    assert L.hull_adjacency_workspace_bytes(fmax + 1, ctypes.byref(out)) == hull.HULL_EINVAL
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    assert L.hull_face_adjacency(fake, fmax + 1, None, None, 1, fake, fake, fake, 1 << 40,
+                                 None) == hull.HULL_EINVAL
