@@ -28,7 +28,9 @@ Also reported on the same line:
   adjacency       face adjacency (half-edge twins) of the n = 2^24 hull's faces
                   and of the 10,000-cloud batch's faces;
   cpu_baseline    the oracle (sequential C, one thread) on a bounded sample of
-                  the n = 2^24 workload.
+                  the n = 2^24 workload, with the host's CPU model and core
+                  count; and the oracle on every 64th cloud of the batch on a
+                  thread pool over the host cores (hulls/s).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg3]
                        [--no-singles] [--no-batched] [--no-diff] [--no-per-hull]
@@ -41,6 +43,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -106,19 +110,58 @@ def timed(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0)), os.cpu_count()
+
+
 def cpu_baseline(p, sample_n):
     """The oracle, as it stands, on the first sample_n rows (rows are in
-    random order, so this is a uniform subsample of the same workload)."""
+    random order, so this is a uniform subsample of the same workload).  The
+    method is sequential: one thread."""
     import oracle
     s = p[:sample_n].copy()
     t = time.perf_counter()
     f = oracle.hull(s)
     dt = time.perf_counter() - t
+    model, avail, total = host_cpu()
     return {"value": round(sample_n / dt / 1e6, 6), "unit": "Mpoints/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "nproc": avail, "cpu_count": total,
             "sample": f"first {sample_n} rows of the n = 2^24 workload (a uniform subsample), "
                       f"lower+upper runs, sequential C oracle on one thread, {dt:.1f} s, "
                       f"{len(f)} faces"}
+
+
+def cpu_batched(workloads, stride=64, max_threads=16):
+    """The oracle on every stride-th cloud of the 10,000-cloud batch (the same
+    size and kind mix), one cloud per task on a thread pool over the host
+    cores this process may use (at most max_threads: the GPU box's share);
+    the C oracle runs outside the Python lock.  Hulls/s and Mpoints/s."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    pts, off, _ = workloads.cfg4()
+    idx = list(range(0, len(off) - 1, stride))
+    clouds = [np.ascontiguousarray(pts[off[h]:off[h + 1]]) for h in idx]
+    clouds.sort(key=len, reverse=True)  # longest first
+    model, avail, total = host_cpu()
+    threads = max(1, min(avail, max_threads))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        faces = sum(len(f) for f in ex.map(oracle.hull, clouds))
+    dt = time.perf_counter() - t
+    npts = sum(len(c) for c in clouds)
+    return {"hulls_per_s": round(len(clouds) / dt, 2), "Mpoints_per_s": round(npts / dt / 1e6, 4),
+            "cores": threads, "kind": "oracle", "cpu_model": model, "nproc": avail,
+            "sample": f"every {stride}th cloud of the 10,000-cloud batch ({len(clouds)} clouds, "
+                      f"{npts} points, {faces} faces), thread pool of {threads}, {dt:.1f} s"}
 
 
 def single(args, hull, workloads):
@@ -202,34 +245,48 @@ def single(args, hull, workloads):
     roofline = levels = None
     S = min(sched.serial_levels, L)
     KL = min(sched.fused_levels, S)  # lowest levels: the LDS-staged kernel
+    W = sched.wave_from if sched.wave_from > 0 else L + 1  # first one-merge-per-wave level
+
+    def kernel_of(k):  # k: 1-based level
+        if k > S:
+            return "parallel strategy (k_par_* kernels, device scans)"
+        if k <= KL:
+            return "k_merge_level_lds"
+        return "k_merge_wave" if k >= W else "k_merge_level"
+
     if golden is not None:
         stats = np.array(golden["level_stats_lower"]) + np.array(golden["level_stats_upper"])
         Bk = 4.0 * stats[:, 0] + 4.0 * stats[:, 1] + 28.0 * stats[:, 2]  # bytes per level
-        levels = [{"level": k + 1,
-                   "kernel": ("k_merge_level_lds" if k < KL else "k_merge_level") if k < S
-                   else "parallel (13 kernels)",
+        levels = [{"level": k + 1, "kernel": kernel_of(k + 1),
                    "ms": round(float(lvl[k]), 4), "algorithmic_bytes": float(Bk[k]),
                    "GBps": round(float(Bk[k]) / (lvl[k] / 1e3) / 1e9, 2),
                    "frac": round(float(Bk[k]) / (lvl[k] / 1e3) / 1e9 / HBM_PEAK_GBS, 6)}
                   for k in range(L)]
-        if S > KL:
-            # k_merge_level: the lane-serial levels above the LDS-staged ones
-            per_launch = float(Bk[KL:S].sum()) / (S - KL)
-            avg_ms = float(lvl[KL:S].mean())
+        # the dominant kernel: the merge kernel with the most time in the step
+        groups = {}
+        for k in range(L):
+            kn = kernel_of(k + 1)
+            if not kn.startswith("parallel"):
+                groups.setdefault(kn, []).append(k)
+        if groups:
+            kern, ks = max(groups.items(), key=lambda t: float(lvl[t[1]].sum()))
+            per_launch = float(Bk[ks].sum()) / len(ks)
+            avg_ms = float(lvl[ks].mean())
             achieved = per_launch / (avg_ms / 1e3) / 1e9
             traffic = None
-            tpath = os.path.join(ROOT, "profiles", f"k_merge_level_{args.workload}_traffic.json")
+            tpath = os.path.join(ROOT, "profiles", f"{kern}_{args.workload}_traffic.json")
             if os.path.exists(tpath):
                 tr = json.load(open(tpath))
                 src = b"".join(open(os.path.join(ROOT, "paper_1205_1171_amd", "csrc", f), "rb").read()
-                               for f in ("merge.hip", "events.hpp", "predicates.hpp"))
+                               for f in ("merge.hip", "merge_wave.hpp", "events.hpp",
+                                         "predicates.hpp"))
                 if (tr.get("source_sha256") == hashlib.sha256(src).hexdigest()
-                        and tr.get("serial_levels") == S and tr.get("lds_levels") == KL):
+                        and tr.get("levels") == [ks[0] + 1, ks[-1] + 1]):
                     traffic = tr.get("hbm_bytes_per_launch")
             roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                        "traffic": traffic, "kernel": "k_merge_level",
-                        "levels": [KL + 1, S], "launches_per_step": S - KL,
+                        "traffic": traffic, "kernel": kern,
+                        "levels": [ks[0] + 1, ks[-1] + 1], "launches_per_step": len(ks),
                         "avg_launch_ms": round(avg_ms, 4),
                         "algorithmic_bytes_per_launch": per_launch,
                         "all_levels_GBps": round(float(Bk.sum()) / (lvl.sum() / 1e3) / 1e9, 3)}
@@ -252,7 +309,8 @@ def single(args, hull, workloads):
                    else f"{args.workload}: n={n}",
                    "n": n, "faces": F, "runs": "lower+upper",
                    "schedule": {"serial_levels": sched.serial_levels,
-                                "walk_segment": sched.walk_segment}},
+                                "walk_segment": sched.walk_segment,
+                                "wave_from": sched.wave_from}},
         "bit_exact": bit_exact,
         "phase_ms": {"sort": round(sort_ms, 4), "merge_levels": [round(v, 4) for v in lvl],
                      "extract": round(extract_ms, 4)},
@@ -627,6 +685,9 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p, min(args.cpu_sample, len(p)))
+        if not args.no_batched:
+            log("cpu batched (oracle, thread pool)")
+            out["cpu_baseline"]["batched"] = cpu_batched(workloads)
     print(json.dumps(out), flush=True)
 
 

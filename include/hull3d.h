@@ -47,7 +47,9 @@ extern "C" {
 #define HULL_OK 0
 #define HULL_EINVAL (-1)     /* null pointer, n out of range, capacity < 2n */
 #define HULL_EWORKSPACE (-2) /* workspace smaller than hull_workspace_bytes() */
-#define HULL_ERANGE (-3)     /* some |coordinate| > 2^29 (reported in d_info[0]) */
+#define HULL_ERANGE (-3)     /* a coordinate outside the entry point's range (reported in
+                                d_info[0]): |c| > 2^29 for int32 rows; see the wide and
+                                float entry points for theirs */
 #define HULL_EHIP (-4)       /* HIP runtime or launch failure */
 #define HULL_EINTERNAL (-5)  /* an internal consistency bound tripped (d_info[0]) */
 
@@ -58,8 +60,14 @@ const char* hull_strerror(int32_t code);
  * if none yet). */
 int32_t hull_last_hip_error(void);
 
-/* Bytes of device workspace that hull_lower / hull_full need for n points
- * (host, synchronous).  flags: reserved, pass 0. */
+/* Workspace kinds for hull_workspace_bytes. */
+#define HULL_WS_STANDARD 0 /* hull_lower, hull_full (int32 rows) */
+#define HULL_WS_WIDE 1     /* hull_lower_wide, hull_full_wide (int64 rows) */
+#define HULL_WS_F32 2      /* hull_full_f32, hull_lower_f32 (float rows) */
+
+/* Bytes of device workspace that the entry points of kind `flags` (one of
+ * HULL_WS_*) need for n points (host, synchronous).  HULL_EINVAL for another
+ * flag value, n < 0 or n > 2^26. */
 int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes);
 
 /* Lower hull: the faces whose outward normal points to negative z (under the
@@ -91,6 +99,36 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
                         int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream,
                         void* const* events, int32_t nevents);
 
+/* The same two calls on the wide coordinate range: int64 rows [n, 3] with
+ * |x|, |y| <= 2^30 and |z| <= 2^42 (beyond the standard range of 2^29; for
+ * instance lifted points (x, y, x^2 + y^2) with |x|, |y| <= 2^20).  Same
+ * method, same perturbation and the same result definition; the orientation
+ * products are taken in int128, and exact ties of the double filter go to
+ * the full 256-bit cascade.  A coordinate outside the range gives HULL_ERANGE
+ * in d_info[0].  Workspace: hull_workspace_bytes(n, HULL_WS_WIDE).  The
+ * paper keeps float coordinates (Sec. 3, Fig. "point_datatypes"); the wide
+ * range is what float input snapped to a 30-bit lattice needs. */
+int32_t hull_lower_wide(const int64_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
+                        int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream);
+int32_t hull_full_wide(const int64_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
+                       int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Float input (the paper's single-precision coordinates, Sec. 3, Fig.
+ * "point_datatypes"): every coordinate of the float32 rows [n, 3] is scaled
+ * by the one power of two s = 2^(bits - E), E the least integer with
+ * max |c| <= 2^E over all 3n coordinates (E = 0 if all are zero), and rounded
+ * to the nearest integer, ties to even; the faces are those of the exact
+ * perturbed hull of these lattice points (as hull_full_wide / hull_lower_wide
+ * on them).  Scaling by a power of two is exact, so the only rounding is the
+ * last step: floats within a factor 2^(bits - 24) of the largest magnitude
+ * keep their value exactly.  bits in [1, 30] (HULL_EINVAL otherwise).  A NaN
+ * or infinite coordinate gives HULL_ERANGE in d_info[0].
+ * Workspace: hull_workspace_bytes(n, HULL_WS_F32). */
+int32_t hull_full_f32(const float* d_xyz, int64_t n, int32_t bits, int32_t* d_faces, int64_t cap,
+                      int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream);
+int32_t hull_lower_f32(const float* d_xyz, int64_t n, int32_t bits, int32_t* d_faces, int64_t cap,
+                       int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream);
+
 /* Merge schedule of a batched call (every field < 0, or 0 for walk_segment,
  * takes the library default):
  *   serial_levels  merge levels 1..serial_levels run one lane per merge (the
@@ -99,24 +137,30 @@ int32_t hull_full_timed(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64
  *   walk_segment   child events per walk segment, >= 4 (default 4)
  *   fused_levels   ignored on input (pass 0 or -1); hull_schedule_defaults
  *                  writes the number of LDS-staged lowest levels here
- *   reserved       pass 0 */
+ *   wave_from      lane-serial levels from this one on run one merge per
+ *                  wavefront instead of one per lane (the six candidates of
+ *                  an iteration on six lanes, child movies through LDS); 0:
+ *                  the default, negative: no level */
 typedef struct hull_schedule_t {
   int32_t serial_levels;
   int32_t walk_segment;
   int32_t fused_levels;
-  int32_t reserved;
+  int32_t wave_from;
 } hull_schedule_t;
 
 /* The schedule the library uses when a call passes none (or leaves a field
  * at its default): the built-in defaults, overridden by the environment
- * variables HULL_SERIAL_LEVELS and HULL_WALK_SEGMENT when set.  On output,
+ * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT and HULL_WAVE_LEVEL when
+ * set.  On output,
  * fused_levels is the number of lowest lane-serial levels that stage each
  * merge's points and links in LDS (a separate kernel from the other
  * lane-serial levels).  Host, synchronous. */
 int32_t hull_schedule_defaults(hull_schedule_t* out);
 
 /* Bytes of device workspace for hull_full_batched over H hulls of
- * total_points points in all (host, synchronous). */
+ * total_points points in all (host, synchronous).  total_points is at most
+ * 2^28 (whose workspace, about 830 bytes per point, fits one GPU's memory);
+ * more returns HULL_EINVAL, as does hull_full_batched. */
 int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* bytes);
 
 /* Full hulls of H independent point clouds in one launch sequence: every
@@ -216,8 +260,9 @@ int32_t hull_delaunay_workspace_bytes(int64_t n, size_t* bytes);
 /* 2-d Delaunay triangulation by lifting: the lower hull of (x, y, x^2 + y^2)
  * (the hull method of Sec. 2 and 3 unchanged; Sec. "Conclusion" names such
  * follow-on algorithms).
- *   d_xy    device int32 [n, 2], |x|, |y| <= 2^14 (so that x^2 + y^2 stays in
- *           the hull's exact range; otherwise HULL_ERANGE in d_info[0])
+ *   d_xy    device int32 [n, 2], |x|, |y| <= 2^20 (lifted z = x^2 + y^2 up to
+ *           2^41: the wide range of hull_lower_wide, which runs the lower
+ *           hull; otherwise HULL_ERANGE in d_info[0])
  *   d_tris  device int32 [cap, 3], cap >= 2n (written: first T rows):
  *           triangles of input indices, counter-clockwise in the plane
  *   d_info  device int64 [2]: status, T

@@ -10,8 +10,12 @@ namespace hull {
 
 constexpr int kNil = -1;
 constexpr int64_t kMaxN = int64_t(1) << 26;      // points of one hull
-constexpr int64_t kMaxTotal = int64_t(1) << 29;  // points of a batch
+// points of a batch: the workspace of 2^28 points (about 830 bytes per
+// point) still fits the 288 GB of one MI355X
+constexpr int64_t kMaxTotal = int64_t(1) << 28;
 constexpr int32_t kMaxCoord = 1 << 29;
+constexpr int64_t kMaxWideXY = int64_t(1) << 30;  // wide range: |x|, |y|
+constexpr int64_t kMaxWideZ = int64_t(1) << 42;   // wide range: |z|
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kTile = kSortThreads * kSortItems;  // keys per radix tile
@@ -21,7 +25,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
 constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
 constexpr int kScanDevGrid = 512;    // tile blocks per job of a device-length scan
-constexpr int kSegKeep = 8;  // bridge events a walk segment keeps from its counting pass
+constexpr int kSegKeep = 2;  // bridge events a walk segment keeps from its counting pass
 constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
 constexpr int kWorkBins = 1024;     // child-event counts told apart when ordering merges
 
@@ -45,12 +49,37 @@ struct Header {
 
 // One movie event: the face (a, w, b) of ranks a < w < b whose middle vertex w
 // enters (kind = 1) or leaves (kind = 0) the kinetic chain, and the standard
-// part of its time.  One 32-byte record, so that an event and its time come
-// in one access.
+// part of its time rounded to float.  One 16-byte record (one vector load);
+// the kind is the top bit of the middle rank (ranks are below 2^29).
 struct __align__(16) Event {
-  int a, w, b, kind;
-  double t;
-  double pad;
+  int a;
+  int wk;  // w | kind << 31
+  int b;
+  float t;  // NaN: not covered by the filter
+  __host__ __device__ int w() const { return wk & 0x7fffffff; }
+  __host__ __device__ int kind() const { return (int)((unsigned)wk >> 31); }
+};
+
+__host__ __device__ inline Event make_event(int a, int w, int b, int kind, double t) {
+  Event e;
+  e.a = a;
+  e.wk = (int)((unsigned)w | ((unsigned)kind << 31));
+  e.b = b;
+  e.t = (float)t;
+  return e;
+}
+
+// A link-change list entry of the parallel merge strategy: the child event's
+// (a, w | kind << 31, b) and a key that is first the event's slot in the input
+// movies (the list's sort key: a movie is in time order) and, once the list
+// is sorted, the bits of its time (the fields of an Event).
+struct __align__(16) Entry {
+  int a;
+  int wk;
+  int b;
+  int key;
+  __host__ __device__ int w() const { return wk & 0x7fffffff; }
+  __host__ __device__ int kind() const { return (int)((unsigned)wk >> 31); }
 };
 
 // Offsets (bytes) of every workspace region for n points in H hulls.
@@ -75,8 +104,9 @@ struct Plan {
   int64_t n, H, tiles, count_len, partial_len, mcap, seg_cap;
 };
 
-// min_seg: the smallest walk segment (child events) the plan must hold.
-Plan make_plan(int64_t n, int64_t H, int min_seg = kMinWalkSegment);
+// min_seg: the smallest walk segment (child events) the plan must hold;
+// pt_bytes: size of a point by rank (16: int4, standard range; 32: WPt, wide).
+Plan make_plan(int64_t n, int64_t H, int min_seg = kMinWalkSegment, int pt_bytes = 16);
 
 // The HIP error behind the last HULL_EHIP of this host thread.
 void note_hip_error(hipError_t e);
@@ -96,18 +126,28 @@ void note_hip_error(hipError_t e);
 inline void clear_stale_hip_error() { (void)hipGetLastError(); }
 
 // One hull (lower and/or upper run) of n points: sort, every merge level,
-// faces (the body of hull_lower / hull_full).
+// faces (the body of hull_lower / hull_full).  int32 rows: the standard
+// range; int64 rows: the wide range (hull_full_wide and friends).
 int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
                   void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
                   void* const* events, int32_t nevents);
+int32_t hull_runs(const int64_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
+                  void* const* events, int32_t nevents);
+
+// Workspace bytes of the wide-range entry points (int64 rows) and of the
+// float entry points (the wide hull plus the snapped rows), for n points.
+size_t wide_workspace_bytes(int64_t n);
+size_t f32_workspace_bytes(int64_t n);
 
 // Clear the device status words (a kernel, so that the call can be captured).
 void init_header(Header* h, hipStream_t s);
 
-// Sort: ranks by (hull, x, index within the hull).  Fills pts (int4 x, y, z,
-// index within the hull, by rank).  hull_off (device [H + 1]) may be NULL for
-// a single hull.
-int32_t sort_points(const int32_t* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
+// Sort: ranks by (hull, x, index within the hull).  Fills pts (PT: int4 x, y,
+// z, index within the hull from int32 rows; WPt from int64 rows, by rank).
+// hull_off (device [H + 1]) may be NULL for a single hull.
+template <class InT, class PT>
+int32_t sort_points(const InT* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
                     const Plan& pl, hipStream_t s);
 
 // Exclusive scans of int32 (in place allowed).  The second form reads its
@@ -124,6 +164,7 @@ struct ScanJob {
   const int32_t* in;
   int32_t* out;
   const int32_t* d_len;
+  int32_t* total;  // if set: receives the sum of in[0, *d_len) (the scan's total)
 };
 struct ScanJobs {
   ScanJob j[kMaxScanJobs];

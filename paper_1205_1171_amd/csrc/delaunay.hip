@@ -1,28 +1,29 @@
 // 2-d Delaunay triangulation by lifting: the lower hull of the points
 // (x, y, x^2 + y^2) projects to the Delaunay triangulation of (x, y) (the
 // widening of the hull named in the paper's future work; the kinetic merge
-// itself is unchanged).  With |x|, |y| <= 2^14 the lifted coordinate stays
-// within the hull's exact integer range (x^2 + y^2 <= 2^29), so the same
-// symbolic perturbation decides every cocircular or collinear tie.
+// itself is unchanged).  With |x|, |y| <= 2^20 the lifted coordinate is at
+// most 2^41, inside the hull's wide range, so the same symbolic perturbation
+// decides every cocircular or collinear tie.
 #include <algorithm>
 
 #include "common.hpp"
 
 namespace hull {
 
-constexpr int32_t kMaxPlanar = 1 << 14;
+constexpr int32_t kMaxPlanar = 1 << 20;
 
-// Lifted points; a coordinate out of range becomes a lifted value the hull's
-// own range check rejects (HULL_ERANGE in d_info[0]).
+// Lifted points as int64 rows; a coordinate out of range becomes a lifted
+// value the hull's own range check rejects (HULL_ERANGE in d_info[0]).
 __global__ void __launch_bounds__(256) k_lift(const int32_t* __restrict__ xy, int64_t n,
-                                              int32_t* __restrict__ xyz) {
+                                              int64_t* __restrict__ xyz) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t x = xy[2 * i], y = xy[2 * i + 1];
     const bool ok = x >= -kMaxPlanar && x <= kMaxPlanar && y >= -kMaxPlanar && y <= kMaxPlanar;
-    xyz[3 * i] = ok ? x : 0;
-    xyz[3 * i + 1] = ok ? y : 0;
-    xyz[3 * i + 2] = ok ? x * x + y * y : kMaxCoord + 1;
+    const int64_t X = ok ? x : 0, Y = ok ? y : 0;
+    xyz[3 * i] = X;
+    xyz[3 * i + 1] = Y;
+    xyz[3 * i + 2] = ok ? X * X + Y * Y : kMaxWideZ + 1;
   }
 }
 
@@ -46,9 +47,9 @@ extern "C" {
 
 int32_t hull_delaunay_workspace_bytes(int64_t n, size_t* bytes) {
   size_t hb = 0;
-  int32_t rc = hull_workspace_bytes(n, 0, &hb);
+  int32_t rc = hull_workspace_bytes(n, HULL_WS_WIDE, &hb);
   if (rc || !bytes) return rc ? rc : HULL_EINVAL;
-  *bytes = hull::round256(hb) + hull::round256((size_t)(n > 0 ? n : 1) * 12);
+  *bytes = hull::round256(hb) + hull::round256((size_t)(n > 0 ? n : 1) * 24);
   return HULL_OK;
 }
 
@@ -61,14 +62,14 @@ int32_t hull_delaunay(const int32_t* d_xy, int64_t n, int32_t* d_tris, int64_t c
   hull::clear_stale_hip_error();
   hipStream_t s = (hipStream_t)stream;
   size_t hb = 0;
-  hull_workspace_bytes(n, 0, &hb);
+  hull_workspace_bytes(n, HULL_WS_WIDE, &hb);
   const size_t head = hull::round256(hb);
-  int32_t* xyz = (int32_t*)((char*)d_ws + head);
+  int64_t* xyz = (int64_t*)((char*)d_ws + head);
   if (n > 0) {
     const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(hull::k_lift, dim3(g), dim3(256), 0, s, d_xy, n, xyz);
   }
-  int32_t rc = hull::hull_runs(n > 0 ? xyz : nullptr, n, d_tris, cap, d_info, d_ws, head, s, true,
+  int32_t rc = hull::hull_runs(n > 0 ? xyz : (const int64_t*)nullptr, n, d_tris, cap, d_info, d_ws, head, s, true,
                                false, nullptr, 0);
   if (rc) return rc;
   hipLaunchKernelGGL(hull::k_ccw, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 255) / 256, 4096))),

@@ -12,8 +12,10 @@ struct Cand {
 };
 
 // Pointers of one run (lower or upper) for the lane-serial merge strategy.
+// pts: the points by rank, int4 (x, y, z, w) on the standard range or WPt on
+// the wide range (the kernels are instantiated for each).
 struct RunPtrs {
-  const int4* pts;
+  const void* pts;
   int* pv0;
   int* nx0;
   int2* lk;  // working links of the level: (pv, nx) of each point
@@ -49,7 +51,8 @@ struct LevelArgs {
 };
 // Exact (time, rank triple) order of two events (cold path).  Arguments
 // go by value so that callers keep their candidates in registers.
-__device__ __noinline__ int tri_cmp_exact(const int4* pts, Tri A, Tri B, int zs) {
+template <class PT>
+__device__ __noinline__ int tri_cmp_exact(const PT* pts, Tri A, Tri B, int zs) {
   Coef ca, cb;
   coef_of(pts[A.a], pts[A.w], pts[A.b], zs, ca);
   coef_of(pts[B.a], pts[B.w], pts[B.b], zs, cb);
@@ -103,8 +106,56 @@ __device__ __forceinline__ int tri_cmp_mid_body(const int4* pts, Tri A, Tri B, i
   return tri_cmp_exact(pts, A, B, zs);
 }
 
+// The same on the wide range, where D0, N0, D1, N1 need int128 and their
+// products may not fit it (N0 D0 up to 2^138): the three coefficients are
+// taken in int128 when every leading term's bit length leaves the products
+// below 2^124 (so that no sum of four overflows), which covers, for
+// instance, all lifted points of |x|, |y| <= 2^20 (N up to 2^70, D up to
+// 2^48); otherwise the full cascade decides.
+struct WLead {
+  i128 d0, n0, d1, n1;
+};
+
+__device__ __forceinline__ WLead lead_of(const WPt& P, const WPt& Q, const WPt& R, int zs) {
+  const int64_t dx1 = (int64_t)Q.x - P.x, dx2 = (int64_t)R.x - P.x;
+  const int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
+  const int64_t dz1 = Q.z - P.z, dz2 = R.z - P.z;
+  const int64_t di1 = Q.w - P.w, di2 = R.w - P.w;
+  WLead L;
+  L.d0 = (i128)dx1 * dy2 - (i128)dx2 * dy1;
+  L.n0 = zs * ((i128)dx1 * dz2 - (i128)dx2 * dz1);
+  L.d1 = (i128)di1 * dy2 - (i128)di2 * dy1;
+  L.n1 = zs * ((i128)di1 * dz2 - (i128)di2 * dz1);
+  return L;
+}
+
+__device__ __forceinline__ int bits128(i128 v) {
+  const u128 u = v < 0 ? (u128)(-v) : (u128)v;
+  const uint64_t hi = (uint64_t)(u >> 64), lo = (uint64_t)u;
+  return hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
+}
+
+__device__ __forceinline__ int tri_cmp_mid_body(const WPt* pts, Tri A, Tri B, int zs) {
+  const WLead a = lead_of(pts[A.a], pts[A.w], pts[A.b], zs);
+  const WLead b = lead_of(pts[B.a], pts[B.w], pts[B.b], zs);
+  const int sa = a.d0 ? (a.d0 > 0 ? 1 : -1) : (a.d1 > 0) - (a.d1 < 0);
+  const int sb = b.d0 ? (b.d0 > 0 ? 1 : -1) : (b.d1 > 0) - (b.d1 < 0);
+  const int mn = max(max(bits128(a.n0), bits128(a.n1)), max(bits128(b.n0), bits128(b.n1)));
+  const int md = max(max(bits128(a.d0), bits128(a.d1)), max(bits128(b.d0), bits128(b.d1)));
+  if (sa && sb && mn + md <= 124) {
+    i128 p = a.n0 * b.d0 - b.n0 * a.d0;
+    if (!p) {
+      p = a.n0 * b.d1 + a.n1 * b.d0 - b.n0 * a.d1 - b.n1 * a.d0;
+      if (!p) p = a.n1 * b.d1 - b.n1 * a.d1;
+    }
+    if (p) return (p > 0 ? 1 : -1) * sa * sb;
+  }
+  return tri_cmp_exact(pts, A, B, zs);
+}
+
 // The mid tier as a call (kernels with many live registers) ...
-__device__ __noinline__ int tri_cmp_mid(const int4* pts, Tri A, Tri B, int zs) {
+template <class PT>
+__device__ __noinline__ int tri_cmp_mid(const PT* pts, Tri A, Tri B, int zs) {
   return tri_cmp_mid_body(pts, A, B, zs);
 }
 
@@ -112,8 +163,8 @@ __device__ __noinline__ int tri_cmp_mid(const int4* pts, Tri A, Tri B, int zs) {
 // then the mid tier (inlined with kInlineMid: the lane-serial merge, where
 // exact standard-part ties are frequent and a call costs more than the
 // registers).
-template <bool kInlineMid = false>
-__device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand& B, int zs) {
+template <bool kInlineMid = false, class PT>
+__device__ __forceinline__ int ev_cmp(const PT* pts, const Cand& A, const Cand& B, int zs) {
   if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
   int s = std_cmp(A.st, B.st);
   if (s) return s;
@@ -121,7 +172,8 @@ __device__ __forceinline__ int ev_cmp(const int4* pts, const Cand& A, const Cand
 }
 
 // Perturbed sign of D when D0 = D1 = 0 (cold path).
-__device__ __noinline__ int d_sign_slow(int4 P, int4 Q, int4 R) {
+template <class PT>
+__device__ __noinline__ int d_sign_slow(PT P, PT Q, PT R) {
   Coef c;
   coef_of(P, Q, R, 1, c);
   return c.dsign;
@@ -137,8 +189,19 @@ __device__ __forceinline__ int d_sign(int4 P, int4 Q, int4 R) {
   return d_sign_slow(P, Q, R);
 }
 
-__device__ __forceinline__ Cand make_cand(const int4* pts, int a, int w, int b, int4 A, int4 W,
-                                          int4 B, int kind, int zs) {
+// The same on the wide range (D0 up to 2^63: int128; D1 up to 2^58).
+__device__ __forceinline__ int d_sign(const WPt& P, const WPt& Q, const WPt& R) {
+  const int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
+  const i128 D0 = (i128)((int64_t)Q.x - P.x) * dy2 - (i128)((int64_t)R.x - P.x) * dy1;
+  if (D0) return D0 > 0 ? 1 : -1;
+  const int64_t D1 = (int64_t)(Q.w - P.w) * dy2 - (int64_t)(R.w - P.w) * dy1;
+  if (D1) return D1 > 0 ? 1 : -1;
+  return d_sign_slow(P, Q, R);
+}
+
+template <class PT>
+__device__ __forceinline__ Cand make_cand(const PT* pts, int a, int w, int b, const PT& A,
+                                          const PT& W, const PT& B, int kind, int zs) {
   Cand c;
   c.t = Tri{a, w, b};
   c.kind = kind;
@@ -158,11 +221,11 @@ __device__ __forceinline__ int find_owner(const int* off, int count, int64_t x) 
 }
 
 __device__ __forceinline__ Cand cand_of(const Event* ev, int64_t q) {
-  const Event& E = ev[q];
+  const Event E = ev[q];
   Cand c;
-  c.t = Tri{E.a, E.w, E.b};
-  c.kind = E.kind;
-  c.st = E.t;
+  c.t = Tri{E.a, E.w(), E.b};
+  c.kind = E.kind();
+  c.st = (double)E.t;
   return c;
 }
 
@@ -171,7 +234,7 @@ __device__ __forceinline__ Cand cand_of(const Event* ev, int64_t q) {
 // events are enumerated into a compact list, and per-point lists exist only
 // for the points those events touch.
 struct ParRun {
-  const int4* pts;
+  const void* pts;  // int4 or WPt, as in RunPtrs
   int* pv0;
   int* nx0;
   const Event* ev_in;
@@ -187,8 +250,8 @@ struct ParRun {
   int* claimR;    // per point: level that allocated its list
   int* claimL;
   int stamp;      // this level's claim stamp: lists of other points are empty
-  Event* entR;    // link-change events grouped by point, time-sorted (kind | slot << 1)
-  Event* entL;
+  Entry* entR;    // link-change events grouped by point, time-sorted (by slot)
+  Entry* entL;
   int* ctr;       // [kCtrSlots]: touched lists; level totals of merges, child events,
                   // walk segments, bridge events
   int* touched;   // (point << 1 | side) of every allocated list
@@ -230,6 +293,7 @@ struct ParLevel {
   int64_t ecap;     // bound on the child events of a level (2n)
 };
 
+template <class PT>
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s);
 
 }  // namespace hull

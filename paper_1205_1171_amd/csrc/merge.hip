@@ -29,6 +29,7 @@
 
 #include "common.hpp"
 #include "events.hpp"
+#include "merge_wave.hpp"
 
 namespace hull {
 
@@ -38,14 +39,15 @@ namespace hull {
 // (Lev, Rev), the merged movie (out) and the -inf link arrays (pv0, nx0) are
 // global and in global ranks.  Returns the merged movie's length, -1 after an
 // internal error.
-__device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, int* nx0, int base,
+template <class PT>
+__device__ __forceinline__ int merge_core(const PT* pts, int2* lk, int* pv0, int* nx0, int base,
                           const Event* Lev, int nL, const Event* Rev, int nR, Event* out,
                           Header* h, int64_t s, int64_t m, int64_t e, int zs) {
   const int64_t cap = 2 * (e - s);
 
   // 1. bridge at t = -inf
   int u = (int)m - 1, v = (int)m;
-  int4 Pu = pts[u], Pv = pts[v];
+  PT Pu = pts[u], Pv = pts[v];
   for (int guard = 0;; ++guard) {
     if (guard > 2 * (e - s) + 4) {
       atomicCAS(&h->err, 0, HULL_EINTERNAL);
@@ -54,7 +56,7 @@ __device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, i
     int w = nx0[v + base];
     if (w != kNil) {
       w -= base;
-      int4 Pw = pts[w];
+      PT Pw = pts[w];
       if (d_sign(Pu, Pv, Pw) < 0) {
         v = w;
         Pv = Pw;
@@ -64,7 +66,7 @@ __device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, i
     w = pv0[u + base];
     if (w != kNil) {
       w -= base;
-      int4 Pw = pts[w];
+      PT Pw = pts[w];
       if (d_sign(Pw, Pu, Pv) < 0) {
         u = w;
         Pu = Pw;
@@ -109,20 +111,15 @@ __device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, i
   double tL = 0.0, tR = 0.0;
   // events hold global ranks: shifted to the arrays' indexing
   const int4 shift = make_int4(base, base, base, 0);
-  if (nL > 0) {
-    EL = *(const int4*)&Lev[0];
-    EL.x -= shift.x;
-    EL.y -= shift.y;
-    EL.z -= shift.z;
-    tL = Lev[0].t;
-  }
-  if (nR > 0) {
-    ER = *(const int4*)&Rev[0];
-    ER.x -= shift.x;
-    ER.y -= shift.y;
-    ER.z -= shift.z;
-    tR = Rev[0].t;
-  }
+  // a child event as (a, w, b, kind) in the arrays' indexing and its time
+  auto load_ev = [&](const Event* E, int4& X, double& t) {
+    const int4 raw = *(const int4*)E;
+    X = make_int4(raw.x - shift.x, (raw.y & 0x7fffffff) - shift.y, raw.z - shift.z,
+                  (int)((unsigned)raw.y >> 31));
+    t = (double)__int_as_float(raw.w);
+  };
+  if (nL > 0) load_ev(&Lev[0], EL, tL);
+  if (nR > 0) load_ev(&Rev[0], ER, tR);
   const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
   for (int64_t it = 0;; ++it) {
     if (it > iter_cap) {
@@ -227,21 +224,9 @@ __device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, i
       // the child's next event, issued now so that its latency overlaps the
       // rest of this iteration
       if (bi == 0) {
-        if (++i < nL) {
-          EL = *(const int4*)&Lev[i];
-          EL.x -= shift.x;
-          EL.y -= shift.y;
-          EL.z -= shift.z;
-          tL = Lev[i].t;
-        }
+        if (++i < nL) load_ev(&Lev[i], EL, tL);
       } else {
-        if (++j < nR) {
-          ER = *(const int4*)&Rev[j];
-          ER.x -= shift.x;
-          ER.y -= shift.y;
-          ER.z -= shift.z;
-          tR = Rev[j].t;
-        }
+        if (++j < nR) load_ev(&Rev[j], ER, tR);
       }
       emit = bi == 0 ? (bw < u) : (bw > v);
       // the event sets nx(a) and pv(b) (and, inserting w, both links of w)
@@ -278,7 +263,7 @@ __device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, i
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      out[k] = Event{ba + base, bw + base, bb + base, bk, bs, 0.0};
+      out[k] = make_event(ba + base, bw + base, bb + base, bk, bs);
       ++k;
     }
   }
@@ -288,6 +273,7 @@ __device__ __forceinline__ int merge_core(const int4* pts, int2* lk, int* pv0, i
   return k;
 }
 
+template <class PT>
 __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int64_t e) {
   const int nL = R.len_in[s], nR = R.len_in[m];
   if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m)) {
@@ -295,11 +281,12 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     R.len_out[s] = 0;
     return;
   }
-  const int k = merge_core(R.pts, R.lk, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+  const int k = merge_core((const PT*)R.pts, R.lk, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
                            R.ev_out + 2 * s, h, s, m, e, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
 }
 
+template <class PT>
 __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const RunPtrs& R = A.run[blockIdx.y];
@@ -314,7 +301,7 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
     R.len_out[s] = 0;
     return;
   }
-  merge_one(R, A.h, s, m, e);
+  merge_one<PT>(R, A.h, s, m, e);
 }
 
 // Lane-serial levels from this one on list their merges in work order; below
@@ -411,9 +398,9 @@ __global__ void __launch_bounds__(256) k_work_place(LevelArgs A) {
 // in LDS: the merge's scattered point and link accesses then stay on chip
 // (global memory serves only the sequential child events and the output).
 // One wavefront per workgroup; a lane touches only its own LDS slice.
-template <int W>
+template <class PT, int W>
 __global__ void __launch_bounds__(64) k_merge_level_lds(LevelArgs A) {
-  __shared__ int4 sp[64 * W];
+  __shared__ PT sp[64 * W];
   __shared__ int2 sl[64 * W];
   const RunPtrs& R = A.run[blockIdx.y];
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -431,11 +418,12 @@ __global__ void __launch_bounds__(64) k_merge_level_lds(LevelArgs A) {
     R.len_out[s] = 0;
     return;
   }
-  int4* P = sp + threadIdx.x * W;
+  PT* P = sp + threadIdx.x * W;
+  const PT* pts = (const PT*)R.pts;
   int2* K = sl + threadIdx.x * W;
   const int w = (int)(e - s), b = (int)s;
   for (int j = 0; j < w; ++j) {
-    P[j] = R.pts[s + j];
+    P[j] = pts[s + j];
     const int pv = R.pv0[s + j], nx = R.nx0[s + j];
     K[j] = make_int2(pv == kNil ? kNil : pv - b, nx == kNil ? kNil : nx - b);
   }
@@ -523,6 +511,27 @@ __global__ void __launch_bounds__(256) k_sched_fill(Sched S, int k) {
   }
 }
 
+// The same schedule for a single hull of n points in one launch (no scans:
+// merge g covers [g 2^k, min((g + 1) 2^k, n))).
+__global__ void __launch_bounds__(256) k_sched_single(Sched S, int k, int64_t n) {
+  const int64_t width = int64_t(1) << k, w = width >> 1;
+  const int64_t nb = (n + w - 1) >> (k - 1);
+  const int64_t merges = nb >> 1;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < merges;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = g * width;
+    S.mlist[g] = make_int2((int)s, (int)(s + width < n ? s + width : n));
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int t = (nb > 1 && (nb & 1)) ? 1 : 0;
+    S.moff[0] = 0;
+    S.moff[1] = (int)merges;
+    S.toff[0] = 0;
+    S.toff[1] = t;
+    if (t) S.tlist[0] = (int)((nb - 1) * w);
+  }
+}
+
 __global__ void k_set_off1(int64_t* off, int64_t n) {
   if (threadIdx.x == 0) {
     off[0] = 0;
@@ -535,7 +544,7 @@ struct ExtractArgs {
   Sched S;
   const Event* ev[2][2];  // [run][buffer]
   const int* len[2][2];
-  const int4* pts;
+  const void* pts;  // int4 or WPt
   int* fcnt;  // [H + 1], scanned in place into face offsets
   int32_t* faces;
   int64_t cap;
@@ -557,7 +566,14 @@ __global__ void __launch_bounds__(256) k_face_count(ExtractArgs X) {
         if (X.ev[1][b]) F += X.len[1][b][o];
       }
     }
-    X.fcnt[h] = F;
+    if (S.H == 1) {  // offsets [0, F] directly, no scan
+      if (h == 0) {
+        X.fcnt[0] = 0;
+        X.fcnt[1] = F;
+      }
+    } else {
+      X.fcnt[h] = F;
+    }
   }
 }
 
@@ -565,7 +581,9 @@ __global__ void __launch_bounds__(256) k_face_count(ExtractArgs X) {
 // D(a, w, b) < 0, a deletion D > 0.  Lower faces need D < 0 for an outward
 // orientation, upper faces D > 0.  Indices are the points' own (within their
 // hull).
+template <class PT>
 __global__ void __launch_bounds__(256) k_extract(ExtractArgs X) {
+  const PT* pts = (const PT*)X.pts;
   const Sched& S = X.S;
   const int64_t total = X.fcnt[S.H];
   const bool over = total > X.cap || total < 0;
@@ -580,8 +598,8 @@ __global__ void __launch_bounds__(256) k_extract(ExtractArgs X) {
     const int nl = X.ev[0][b] ? X.len[0][b][o] : 0;
     const bool lower = q < nl;
     const Event E = lower ? X.ev[0][b][2 * o + q] : X.ev[1][b][2 * o + (q - nl)];
-    const bool keep = lower ? E.kind == 1 : E.kind == 0;
-    const int a = X.pts[E.a].w, w = X.pts[E.w].w, c = X.pts[E.b].w;
+    const bool keep = lower ? E.kind() == 1 : E.kind() == 0;
+    const int a = pts[E.a].w, w = pts[E.w()].w, c = pts[E.b].w;
     X.faces[3 * t + 0] = a;
     X.faces[3 * t + 1] = keep ? w : c;
     X.faces[3 * t + 2] = keep ? c : w;
@@ -621,9 +639,9 @@ __global__ void __launch_bounds__(256)
          q += (int64_t)gridDim.x * blockDim.x) {
       Event E = ev[2 * s + q];
       d_ev[4 * (2 * s + q) + 0] = E.a;
-      d_ev[4 * (2 * s + q) + 1] = E.w;
+      d_ev[4 * (2 * s + q) + 1] = E.w();
       d_ev[4 * (2 * s + q) + 2] = E.b;
-      d_ev[4 * (2 * s + q) + 3] = E.kind;
+      d_ev[4 * (2 * s + q) + 3] = E.kind();
     }
   }
 }
@@ -654,6 +672,8 @@ static int env_int(const char* name, int dflt) {
 // HULL_WALK_SEGMENT), then defaults.
 struct Opts {
   int serial_max, seg;
+  int wave_from;   // first lane-serial level run by lane groups (0: none)
+  int wave_lanes;  // lanes per merge there: 16, 32 or 64
 };
 
 static Opts resolve(const hull_schedule_t* sc) {
@@ -661,10 +681,15 @@ static Opts resolve(const hull_schedule_t* sc) {
   o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 9);
   o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 4);
   if (o.seg < kMinWalkSegment) o.seg = kMinWalkSegment;
+  const int wf = sc && sc->wave_from != 0 ? sc->wave_from : env_int("HULL_WAVE_LEVEL", 0);
+  o.wave_from = wf > 0 ? std::max(wf, kLdsLevels + 1) : 0;
+  const int wl = env_int("HULL_WAVE_LANES", 16);
+  o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
   return o;
 }
 
 // Runs `levels` merge levels of the selected runs over the hulls of S.
+template <class PT>
 static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, hipStream_t s,
                           bool lower, bool upper, int levels, const Opts& opt,
                           hipEvent_t* events) {
@@ -690,7 +715,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
   for (int r = 0; r < 2; ++r) {
     bool on = r == 0 ? lower : upper;
     RunPtrs& R = A.run[r];
-    R.pts = on ? (const int4*)(ws + pl.pts) : nullptr;
+    R.pts = on ? (const void*)(ws + pl.pts) : nullptr;
     R.pv0 = (int*)(ws + pl.pv0[r]);
     R.nx0 = (int*)(ws + pl.nx0[r]);
     R.lk = (int2*)(ws + pl.lk[r]);
@@ -708,8 +733,8 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     Q.curL = (int*)(ws + pl.curL[r]);
     Q.claimR = (int*)(ws + pl.claimR[r]);
     Q.claimL = (int*)(ws + pl.claimL[r]);
-    Q.entR = (Event*)(ws + pl.entR[r]);
-    Q.entL = (Event*)(ws + pl.entL[r]);
+    Q.entR = (Entry*)(ws + pl.entR[r]);
+    Q.entL = (Entry*)(ws + pl.entL[r]);
     Q.ctr = (int*)(ws + pl.ctr[r]);
     Q.touched = (int*)(ws + pl.touched[r]);
     Q.ecnt = (int*)(ws + pl.ecnt[r]);
@@ -749,12 +774,19 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     A.half = A.width >> 1;
     const bool serial = k <= opt.serial_max;
     // the schedule of this level
-    hipLaunchKernelGGL(k_sched_count, dim3(hgrid), dim3(256), 0, s, S, k, mcnt, tcnt);
-    int32_t rc = exclusive_scan_i32(mcnt, S.moff, S.H + 1, partials, s);
-    if (!rc) rc = exclusive_scan_i32(tcnt, S.toff, S.H + 1, partials, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_sched_fill, dim3(grid_for(std::min<int64_t>(pl.mcap, n / A.width + S.H + 1))),
-                       dim3(256), 0, s, S, k);
+    int32_t rc = HULL_OK;
+    const bool single = S.H == 1;
+    if (single) {
+      hipLaunchKernelGGL(k_sched_single, dim3(grid_for(n / A.width + 1)), dim3(256), 0, s, S, k,
+                         n);
+    } else {
+      hipLaunchKernelGGL(k_sched_count, dim3(hgrid), dim3(256), 0, s, S, k, mcnt, tcnt);
+      rc = exclusive_scan_i32(mcnt, S.moff, S.H + 1, partials, s);
+      if (!rc) rc = exclusive_scan_i32(tcnt, S.toff, S.H + 1, partials, s);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_sched_fill, dim3(grid_for(std::min<int64_t>(pl.mcap, n / A.width + S.H + 1))),
+                         dim3(256), 0, s, S, k);
+    }
     for (int r = 0; r < 2; ++r) {
       RunPtrs& R = A.run[r];
       R.ev_in = (const Event*)(ws + pl.ev[r][buf]);
@@ -773,10 +805,10 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     if (serial && k <= kLdsLevels) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 63) / 64), 2);
-      if (k == 1) hipLaunchKernelGGL(k_merge_level_lds<2>, grid, dim3(64), 0, s, A);
-      else if (k == 2) hipLaunchKernelGGL(k_merge_level_lds<4>, grid, dim3(64), 0, s, A);
-      else if (k == 3) hipLaunchKernelGGL(k_merge_level_lds<8>, grid, dim3(64), 0, s, A);
-      else hipLaunchKernelGGL(k_merge_level_lds<16>, grid, dim3(64), 0, s, A);
+      if (k == 1) hipLaunchKernelGGL((k_merge_level_lds<PT, 2>), grid, dim3(64), 0, s, A);
+      else if (k == 2) hipLaunchKernelGGL((k_merge_level_lds<PT, 4>), grid, dim3(64), 0, s, A);
+      else if (k == 3) hipLaunchKernelGGL((k_merge_level_lds<PT, 8>), grid, dim3(64), 0, s, A);
+      else hipLaunchKernelGGL((k_merge_level_lds<PT, 16>), grid, dim3(64), 0, s, A);
     } else if (serial) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 255) / 256), 2);
@@ -791,16 +823,30 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
         hipLaunchKernelGGL(k_work_scan, dim3(1, 2), dim3(64), 0, s, B);
         hipLaunchKernelGGL(k_work_place, grid, dim3(256), 0, s, B);
       }
-      hipLaunchKernelGGL(k_merge_level, grid, dim3(256), 0, s, B);
+      if (opt.wave_from > 0 && k >= opt.wave_from) {
+        const int per = 256 / opt.wave_lanes;  // merges per block
+        const dim3 wg((unsigned)((bound + per - 1) / per), 2);
+        if (opt.wave_lanes == 64) hipLaunchKernelGGL((k_merge_wave<PT, 64>), wg, dim3(256), 0, s, B);
+        else if (opt.wave_lanes == 32)
+          hipLaunchKernelGGL((k_merge_wave<PT, 32>), wg, dim3(256), 0, s, B);
+        else if (opt.wave_lanes == 16)
+          hipLaunchKernelGGL((k_merge_wave<PT, 16>), wg, dim3(256), 0, s, B);
+        else hipLaunchKernelGGL((k_merge_wave<PT, 8>), wg, dim3(256), 0, s, B);
+      } else
+        hipLaunchKernelGGL(k_merge_level<PT>, grid, dim3(256), 0, s, B);
     } else {
       P.k = k;
       P.run[0].stamp = P.run[1].stamp = k;
-      rc = parallel_level(P, partials, s);
+      rc = parallel_level<PT>(P, partials, s);
       if (rc) return rc;
     }
     if (events) (void)hipEventRecord(events[2 * k + 1], s);
-    hipLaunchKernelGGL(k_passthrough, dim3((unsigned)std::min<int64_t>(S.H, 4096), 2), dim3(256),
-                       0, s, A);
+    // a single hull has a trailing block at this level when its block count
+    // is odd and above one
+    const int64_t nb = (n + A.half - 1) / A.half;
+    if (!single || (nb > 1 && (nb & 1)))
+      hipLaunchKernelGGL(k_passthrough, dim3((unsigned)std::min<int64_t>(S.H, 4096), 2), dim3(256),
+                         0, s, A);
     HULL_LAUNCH_CHECK();
     buf ^= 1;
   }
@@ -808,6 +854,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
 }
 
 // Faces of every hull of S after its merges.
+template <class PT>
 static int32_t extract(const Sched& S, char* ws, const Plan& pl, hipStream_t s, bool lower,
                        bool upper, int32_t* d_faces, int64_t cap, int64_t* d_face_off,
                        int64_t* d_info) {
@@ -819,7 +866,7 @@ static int32_t extract(const Sched& S, char* ws, const Plan& pl, hipStream_t s, 
       X.ev[r][b] = on ? (const Event*)(ws + pl.ev[r][b]) : nullptr;
       X.len[r][b] = (const int*)(ws + pl.len[r][b]);
     }
-  X.pts = (const int4*)(ws + pl.pts);
+  X.pts = (const void*)(ws + pl.pts);
   X.fcnt = (int*)(ws + pl.fcnt);
   X.faces = d_faces;
   X.cap = cap;
@@ -828,24 +875,27 @@ static int32_t extract(const Sched& S, char* ws, const Plan& pl, hipStream_t s, 
   X.h = (const Header*)(ws + pl.header);
   int32_t* partials = (int32_t*)(ws + pl.partials);
   hipLaunchKernelGGL(k_face_count, dim3(grid_for(S.H + 1, 1024)), dim3(256), 0, s, X);
-  int32_t rc = exclusive_scan_i32(X.fcnt, X.fcnt, S.H + 1, partials, s);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_extract, dim3(grid_for(std::max<int64_t>(cap, S.H + 1), 2048)), dim3(256), 0,
+  if (S.H > 1) {  // one hull: k_face_count writes the offsets themselves
+    int32_t rc = exclusive_scan_i32(X.fcnt, X.fcnt, S.H + 1, partials, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_extract<PT>, dim3(grid_for(std::max<int64_t>(cap, S.H + 1), 2048)), dim3(256), 0,
                      s, X);
   HULL_LAUNCH_CHECK();
   return HULL_OK;
 }
 
-int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
-                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
-                  void* const* events, int32_t nevents) {
+template <class InT, class PT>
+static int32_t hull_runs_t(const InT* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
+                           int64_t* d_info, void* d_ws, size_t ws_bytes, hipStream_t s, bool lower,
+                           bool upper, void* const* events, int32_t nevents) {
   if (n < 0 || n > kMaxN || !d_info || (n > 0 && !d_xyz) || !d_faces || cap < 2 * n || !d_ws)
     return HULL_EINVAL;
   const int L = levels_for(n);
   if (events && nevents < 2 * L + 3) return HULL_EINVAL;
   hipEvent_t* ev = (hipEvent_t*)events;
   const Opts opt = resolve(nullptr);
-  Plan pl = make_plan(n, 1, opt.seg);
+  Plan pl = make_plan(n, 1, opt.seg, (int)sizeof(PT));
   if (ws_bytes < pl.total) return HULL_EWORKSPACE;
   char* ws = (char*)d_ws;
   Header* h = (Header*)(ws + pl.header);
@@ -863,15 +913,29 @@ int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap
   Sched S{};
   S.off = off;
   S.H = 1;
-  int32_t rc = sort_points(d_xyz, n, nullptr, 1, ws, pl, s);
+  int32_t rc = sort_points<InT, PT>(d_xyz, n, nullptr, 1, ws, pl, s);
   if (rc) return rc;
   if (ev) (void)hipEventRecord(ev[1], s);
-  rc = run_levels(n, S, ws, pl, s, lower, upper, L, opt, ev);
+  rc = run_levels<PT>(n, S, ws, pl, s, lower, upper, L, opt, ev);
   if (rc) return rc;
   S.moff = (int*)(ws + pl.moff);
-  rc = extract(S, ws, pl, s, lower, upper, d_faces, cap, nullptr, d_info);
+  rc = extract<PT>(S, ws, pl, s, lower, upper, d_faces, cap, nullptr, d_info);
   if (ev) (void)hipEventRecord(ev[2 * L + 2], s);
   return rc;
+}
+
+int32_t hull_runs(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
+                  void* const* events, int32_t nevents) {
+  return hull_runs_t<int32_t, int4>(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, s, lower,
+                                    upper, events, nevents);
+}
+
+int32_t hull_runs(const int64_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap, int64_t* d_info,
+                  void* d_ws, size_t ws_bytes, hipStream_t s, bool lower, bool upper,
+                  void* const* events, int32_t nevents) {
+  return hull_runs_t<int64_t, WPt>(d_xyz, n, d_faces, cap, d_info, d_ws, ws_bytes, s, lower, upper,
+                                   events, nevents);
 }
 
 int32_t batched(const int32_t* d_xyz, const int64_t* d_off, const int64_t* h_off, int64_t H,
@@ -881,13 +945,13 @@ int32_t batched(const int32_t* d_xyz, const int64_t* d_off, const int64_t* h_off
   const int64_t n = h_off[H];
   if (h_off[0] != 0 || n < 0 || n > kMaxTotal || (n > 0 && !d_xyz) || cap < 2 * n)
     return HULL_EINVAL;
+  const Opts opt = resolve(sched);
   int L = 0;
   for (int64_t q = 0; q < H; ++q) {
     const int64_t nh = h_off[q + 1] - h_off[q];
     if (nh < 0 || nh > kMaxN) return HULL_EINVAL;
     L = std::max(L, levels_for(nh));
   }
-  const Opts opt = resolve(sched);
   Plan pl = make_plan(n, H, opt.seg);
   if (ws_bytes < pl.total) return HULL_EWORKSPACE;
   char* ws = (char*)d_ws;
@@ -897,9 +961,9 @@ int32_t batched(const int32_t* d_xyz, const int64_t* d_off, const int64_t* h_off
   S.off = d_off;
   S.H = H;
   if (n > 0) {
-    int32_t rc = sort_points(d_xyz, n, d_off, H, ws, pl, s);
+    int32_t rc = sort_points<int32_t, int4>(d_xyz, n, d_off, H, ws, pl, s);
     if (rc) return rc;
-    rc = run_levels(n, S, ws, pl, s, true, true, L, opt, nullptr);
+    rc = run_levels<int4>(n, S, ws, pl, s, true, true, L, opt, nullptr);
     if (rc) return rc;
   } else {
     for (int r = 0; r < 2; ++r)
@@ -907,7 +971,7 @@ int32_t batched(const int32_t* d_xyz, const int64_t* d_off, const int64_t* h_off
                          (int*)(ws + pl.nx0[r]), (int*)(ws + pl.len[r][0]),
                          (int*)(ws + pl.claimR[r]), (int*)(ws + pl.claimL[r]), int64_t(1));
   }
-  return extract(S, ws, pl, s, true, true, d_faces, cap, d_face_off, d_info);
+  return extract<int4>(S, ws, pl, s, true, true, d_faces, cap, d_face_off, d_info);
 }
 
 int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int32_t* d_ev,
@@ -927,11 +991,11 @@ int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int3
   Sched S{};
   S.off = off;
   S.H = 1;
-  int32_t rc = sort_points(d_xyz, n, nullptr, 1, ws, pl, s);
+  int32_t rc = sort_points<int32_t, int4>(d_xyz, n, nullptr, 1, ws, pl, s);
   if (rc) return rc;
   int L = levels_for(n);
   if (level >= 0 && level < L) L = level;
-  rc = run_levels(n, S, ws, pl, s, run == 0, run == 1, L, opt, nullptr);
+  rc = run_levels<int4>(n, S, ws, pl, s, run == 0, run == 1, L, opt, nullptr);
   if (rc) return rc;
   hipLaunchKernelGGL(k_export_movies, dim3(grid_for(2 * n, 1024)), dim3(256), 0, s,
                      (const Event*)(ws + pl.ev[run][L & 1]), (const int*)(ws + pl.len[run][L & 1]),
@@ -951,7 +1015,7 @@ const char* hull_strerror(int32_t code) {
     case HULL_OK: return "ok";
     case HULL_EINVAL: return "invalid argument";
     case HULL_EWORKSPACE: return "workspace too small";
-    case HULL_ERANGE: return "coordinate outside [-2^29, 2^29]";
+    case HULL_ERANGE: return "coordinate outside the supported range (or not finite)";
     case HULL_EHIP: return "HIP runtime error";
     case HULL_EINTERNAL: return "internal consistency bound exceeded";
     default: return "unknown status";
@@ -959,9 +1023,13 @@ const char* hull_strerror(int32_t code) {
 }
 
 int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes) {
-  (void)flags;
   if (!bytes || n < 0 || n > hull::kMaxN) return HULL_EINVAL;
-  *bytes = hull::make_plan(n, 1, hull::kMinWalkSegment).total;
+  switch (flags) {
+    case HULL_WS_STANDARD: *bytes = hull::make_plan(n, 1, hull::kMinWalkSegment).total; break;
+    case HULL_WS_WIDE: *bytes = hull::wide_workspace_bytes(n); break;
+    case HULL_WS_F32: *bytes = hull::f32_workspace_bytes(n); break;
+    default: return HULL_EINVAL;
+  }
   return HULL_OK;
 }
 
@@ -971,7 +1039,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
   out->serial_levels = o.serial_max;
   out->walk_segment = o.seg;
   out->fused_levels = hull::kLdsLevels;
-  out->reserved = 0;
+  out->wave_from = o.wave_from;
   return HULL_OK;
 }
 

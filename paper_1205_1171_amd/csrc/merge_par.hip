@@ -29,7 +29,8 @@
 namespace hull {
 
 // # of events among slots [base, base + len) strictly before X.
-__device__ int count_before(const int4* pts, const Event* ev, int64_t base, int len, const Cand& X,
+template <class PT>
+__device__ int count_before(const PT* pts, const Event* ev, int64_t base, int len, const Cand& X,
                             int zs) {
   int lo = 0, hi = len;
   while (lo < hi) {
@@ -41,48 +42,52 @@ __device__ int count_before(const int4* pts, const Event* ev, int64_t base, int 
   return lo;
 }
 
-// Sort one point's entries by slot (= time order within the child movie).
-__device__ void sort_entries(Event* a, int k) {
+// Sort one point's entries by slot (= time order within the child movie),
+// then replace each slot by the event's time.
+__device__ void sort_entries(Entry* a, int k, const Event* ev) {
   int gap = 1;
   while (gap < k / 3) gap = 3 * gap + 1;
   for (; gap > 0; gap /= 3)
     for (int i = gap; i < k; ++i) {
-      Event x = a[i];
+      Entry x = a[i];
       int j = i;
-      while (j >= gap && a[j - gap].kind > x.kind) {
+      while (j >= gap && a[j - gap].key > x.key) {
         a[j] = a[j - gap];
         j -= gap;
       }
       a[j] = x;
     }
+  for (int i = 0; i < k; ++i) a[i].key = __float_as_int(ev[a[i].key].t);
 }
 
 // Link of p after an event that changes it.
-__device__ __forceinline__ int right_after(const Event& E, int p) {
-  return p == E.a ? ((E.kind & 1) ? E.w : E.b) : E.b;
+__device__ __forceinline__ int right_after(const Entry& E, int p) {
+  return p == E.a ? (E.kind() ? E.w() : E.b) : E.b;
 }
-__device__ __forceinline__ int left_after(const Event& E, int p) {
-  return p == E.b ? ((E.kind & 1) ? E.w : E.a) : E.a;
+__device__ __forceinline__ int left_after(const Entry& E, int p) {
+  return p == E.b ? (E.kind() ? E.w() : E.a) : E.a;
 }
 
-__device__ __forceinline__ Cand cand_entry(const Event* e, int j) {
-  const Event& E = e[j];
+// A sorted entry as a candidate (its key holds the time).
+__device__ __forceinline__ Cand cand_entry(const Entry* e, int j) {
+  const Entry E = e[j];
   Cand c;
-  c.t = Tri{E.a, E.w, E.b};
-  c.kind = E.kind & 1;
-  c.st = E.t;
+  c.t = Tri{E.a, E.w(), E.b};
+  c.kind = E.kind();
+  c.st = (double)__int_as_float(E.key);
   return c;
 }
 
 // Position in a point's list of its first change strictly after T.
-__device__ int first_after(const ParRun& R, const Event* e, int off, int cnt, bool haveT,
+template <class PT>
+__device__ int first_after(const ParRun& R, const Entry* e, int off, int cnt, bool haveT,
                            const Cand& T) {
   if (!haveT) return 0;
   int lo = 0, hi = cnt;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
     Cand c = cand_entry(e, off + mid);
-    if (ev_cmp(R.pts, c, T, R.zs) > 0) hi = mid;
+    if (ev_cmp((const PT*)R.pts, c, T, R.zs) > 0) hi = mid;
     else lo = mid + 1;
   }
   return lo;
@@ -95,6 +100,7 @@ struct Endpoint {
   int oR, nR, oL, nL;
 };
 
+template <class PT>
 __device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) {
   int p = X.p;
   // a point no child event touched at this level has empty lists (its
@@ -104,31 +110,33 @@ __device__ void lookup(const ParRun& R, Endpoint& X, bool haveT, const Cand& T) 
   X.nR = hasR ? R.cntR[p] : 0;
   X.oL = hasL ? R.offL[p] : 0;
   X.nL = hasL ? R.cntL[p] : 0;
-  X.cr = first_after(R, R.entR, X.oR, X.nR, haveT, T);
-  X.cl = first_after(R, R.entL, X.oL, X.nL, haveT, T);
+  X.cr = first_after<PT>(R, R.entR, X.oR, X.nR, haveT, T);
+  X.cl = first_after<PT>(R, R.entL, X.oL, X.nL, haveT, T);
   X.nx = X.cr > 0 ? right_after(R.entR[X.oR + X.cr - 1], p) : R.nx0[p];
   X.pv = X.cl > 0 ? left_after(R.entL[X.oL + X.cl - 1], p) : R.pv0[p];
 }
 
 // One link of p just after T (the right link with `right`), without the rest
 // of the endpoint state: the tangent search needs only that.
+template <class PT>
 __device__ int link_after(const ParRun& R, int p, bool right, bool haveT, const Cand& T) {
   if (right) {
     if (R.claimR[p] != R.stamp) return R.nx0[p];
     const int o = R.offR[p];
-    const int c = first_after(R, R.entR, o, R.cntR[p], haveT, T);
+    const int c = first_after<PT>(R, R.entR, o, R.cntR[p], haveT, T);
     return c > 0 ? right_after(R.entR[o + c - 1], p) : R.nx0[p];
   }
   if (R.claimL[p] != R.stamp) return R.pv0[p];
   const int o = R.offL[p];
-  const int c = first_after(R, R.entL, o, R.cntL[p], haveT, T);
+  const int c = first_after<PT>(R, R.entL, o, R.cntL[p], haveT, T);
   return c > 0 ? left_after(R.entL[o + c - 1], p) : R.pv0[p];
 }
 
 // Orientation of the rank-ordered triple (a, b, c) just after event T: its
 // sign at t = -inf is sign(D), and it flips once, at its own event.
-__device__ int orient_after(const int4* pts, int a, int b, int c, const Cand& T, int zs) {
-  int4 A = pts[a], B = pts[b], C = pts[c];
+template <class PT>
+__device__ int orient_after(const PT* pts, int a, int b, int c, const Cand& T, int zs) {
+  const PT A = pts[a], B = pts[b], C = pts[c];
   int ds = d_sign(A, B, C);
   Cand x = make_cand(pts, a, b, c, A, B, C, 0, zs);
   return ev_cmp(pts, x, T, zs) > 0 ? ds : -ds;
@@ -141,14 +149,16 @@ __device__ int orient_after(const int4* pts, int a, int b, int c, const Cand& T,
 // events of the two movies together.  Found by a co-rank search: the number
 // jL of left-movie events among the first k = floor(i * N / S) is the first
 // j at which L[j] comes after R[k-1-j].  Returns b_i's input-movie slot.
+template <class PT>
 __device__ int64_t boundary_slot(const ParRun& R, int64_t s, int64_t m, int i, int S) {
+  const PT* pts = (const PT*)R.pts;
   const int nL = R.len_in[s], nR = R.len_in[m];
   const int64_t N = (int64_t)nL + nR;
   const int k = (int)((int64_t)i * N / S);
   int lo = k - nR > 0 ? k - nR : 0, hi = k < nL ? k : nL;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (ev_cmp(R.pts, cand_of(R.ev_in, 2 * s + mid), cand_of(R.ev_in, 2 * m + (k - 1 - mid)),
+    if (ev_cmp(pts, cand_of(R.ev_in, 2 * s + mid), cand_of(R.ev_in, 2 * m + (k - 1 - mid)),
                R.zs) < 0)
       lo = mid + 1;
     else
@@ -158,7 +168,7 @@ __device__ int64_t boundary_slot(const ParRun& R, int64_t s, int64_t m, int i, i
   if (jL == 0) return 2 * m + jR - 1;
   if (jR == 0) return 2 * s + jL - 1;
   const int64_t a = 2 * s + jL - 1, b = 2 * m + jR - 1;
-  return ev_cmp(R.pts, cand_of(R.ev_in, a), cand_of(R.ev_in, b), R.zs) > 0 ? a : b;
+  return ev_cmp(pts, cand_of(R.ev_in, a), cand_of(R.ev_in, b), R.zs) > 0 ? a : b;
 }
 
 __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
@@ -171,11 +181,12 @@ __device__ __forceinline__ int segments_for(int nL, int nR, int G) {
 // events in the segment; with `out` set, writes them there (and their
 // bridges after each move to `out_uv`).  Segment 0 also reports the -inf
 // bridge in `uv0`.
+template <class PT>
 __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, int64_t e,
                             int64_t b0, int64_t b1, Event* out, int2* out_uv, int cap,
                             int2* uv0, int2* start_uv, bool have_start, Event* keep = nullptr,
                             int2* keep_uv = nullptr, const Event* resume = nullptr) {
-  const int4* pts = R.pts;
+  const PT* pts = (const PT*)R.pts;
   const int zs = R.zs;
   bool haveT = false, haveEnd = false;
   Cand T, Tend;
@@ -207,7 +218,7 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
       return 0;
     }
   } else {
-    int vnx = link_after(R, vp, true, haveT, T), upv = link_after(R, up, false, haveT, T);
+    int vnx = link_after<PT>(R, vp, true, haveT, T), upv = link_after<PT>(R, up, false, haveT, T);
     for (int guard = 0;; ++guard) {
       if (guard > 2 * (e - s) + 4) {
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
@@ -217,7 +228,7 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
         int o = haveT ? orient_after(pts, up, vp, vnx, T, zs) : d_sign(pts[up], pts[vp], pts[vnx]);
         if (o < 0) {
           vp = vnx;
-          vnx = link_after(R, vp, true, haveT, T);
+          vnx = link_after<PT>(R, vp, true, haveT, T);
           continue;
         }
       }
@@ -225,7 +236,7 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
         int o = haveT ? orient_after(pts, upv, up, vp, T, zs) : d_sign(pts[upv], pts[up], pts[vp]);
         if (o < 0) {
           up = upv;
-          upv = link_after(R, up, false, haveT, T);
+          upv = link_after<PT>(R, up, false, haveT, T);
           continue;
         }
       }
@@ -234,10 +245,10 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
     if (start_uv) *start_uv = make_int2(up, vp);
   }
   Endpoint U{up, 0, 0, 0, 0, 0, 0, 0, 0}, V{vp, 0, 0, 0, 0, 0, 0, 0, 0};
-  lookup(R, U, haveT, T);
-  lookup(R, V, haveT, T);
+  lookup<PT>(R, U, haveT, T);
+  lookup<PT>(R, V, haveT, T);
   if (uv0) *uv0 = make_int2(U.p, V.p);
-  int4 Pu = pts[U.p], Pv = pts[V.p];
+  PT Pu = pts[U.p], Pv = pts[V.p];
   int nb = 0;
   const int64_t iter_cap = (int64_t)R.len_in[s] + R.len_in[m] + 4 * (e - s) + 16;
   for (int64_t it = 0;; ++it) {
@@ -301,20 +312,20 @@ __device__ int walk_segment(const ParRun& R, Header* h, int64_t s, int64_t m, in
     else V.p = V.nx;
     if (bi <= 1) {
       Pu = pts[U.p];
-      lookup(R, U, true, T);
+      lookup<PT>(R, U, true, T);
     } else {
       Pv = pts[V.p];
-      lookup(R, V, true, T);
+      lookup<PT>(R, V, true, T);
     }
     if (out) {
       if (nb >= cap) {
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      out[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind, T.st, 0.0};
+      out[nb] = make_event(T.t.a, T.t.w, T.t.b, T.kind, T.st);
       out_uv[nb] = make_int2(U.p, V.p);
     } else if (keep && nb < kSegKeep) {
-      keep[nb] = Event{T.t.a, T.t.w, T.t.b, T.kind, T.st, 0.0};
+      keep[nb] = make_event(T.t.a, T.t.w, T.t.b, T.kind, T.st);
       keep_uv[nb] = make_int2(U.p, V.p);
     }
     ++nb;
@@ -350,29 +361,27 @@ __global__ void __launch_bounds__(256) k_par_prep(ParLevel P) {
   }
 }
 
-// Level totals after the scans: child events and walk segments.
-__global__ void k_par_totals(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts || threadIdx.x) return;
-  const int merges = R.ctr[kCtrMerges];
-  R.ctr[kCtrEvents] = R.eoff[merges];
-  R.ctr[kCtrSegments] = R.segBase[merges];
-}
-
-__global__ void k_par_btotal(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts || threadIdx.x) return;
-  R.ctr[kCtrBridge] = R.boff[R.ctr[kCtrMerges]];
-}
-
 // The compact list of child events (slot and merge of each), and the
-// link-change counters of their points cleared.
+// link-change counters of their points cleared; then, past the events, the
+// segment table: per walk segment its merge and the slot of the child event
+// it starts after.
+template <class PT>
 __global__ void __launch_bounds__(256) k_par_enum(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
-  const int merges = R.ctr[kCtrMerges], E = R.ctr[kCtrEvents];
+  const int merges = R.ctr[kCtrMerges], E = R.ctr[kCtrEvents], Sg = R.ctr[kCtrSegments];
   const int64_t half = int64_t(1) << (P.k - 1);
-  GRID_STRIDE(c, E) {
+  const bool err = P.h->err != 0;
+  GRID_STRIDE(c, (int64_t)E + Sg) {
+    if (c >= E) {
+      const int64_t t = c - E;
+      const int g = find_owner(R.segBase, merges, t);
+      R.segMerge[t] = g;
+      const int i = (int)(t - R.segBase[g]);
+      const int64_t s = P.S.mlist[g].x;
+      R.segB[t] = i == 0 || err ? -1 : (int)boundary_slot<PT>(R, s, s + half, i, R.segS[g]);
+      continue;
+    }
     const int g = find_owner(R.eoff, merges, c);
     const int2 se = P.S.mlist[g];
     const int64_t s = se.x, m = s + half;
@@ -386,11 +395,11 @@ __global__ void __launch_bounds__(256) k_par_enum(ParLevel P) {
     R.curR[X.a] = 0;
     R.cntL[X.b] = 0;
     R.curL[X.b] = 0;
-    if (X.kind) {
-      R.cntR[X.w] = 0;
-      R.curR[X.w] = 0;
-      R.cntL[X.w] = 0;
-      R.curL[X.w] = 0;
+    if (X.kind()) {
+      R.cntR[X.w()] = 0;
+      R.curR[X.w()] = 0;
+      R.cntL[X.w()] = 0;
+      R.curL[X.w()] = 0;
     }
   }
 }
@@ -404,9 +413,9 @@ __global__ void __launch_bounds__(256) k_par_count(ParLevel P) {
     const Event X = R.ev_in[R.cslot[c]];
     atomicAdd(&R.cntR[X.a], 1);
     atomicAdd(&R.cntL[X.b], 1);
-    if (X.kind) {
-      atomicAdd(&R.cntR[X.w], 1);
-      atomicAdd(&R.cntL[X.w], 1);
+    if (X.kind()) {
+      atomicAdd(&R.cntR[X.w()], 1);
+      atomicAdd(&R.cntL[X.w()], 1);
     }
   }
 }
@@ -436,14 +445,14 @@ __global__ void __launch_bounds__(256) k_par_claim(ParLevel P) {
       bits |= 4u;
       nL += R.cntL[X.b];
     }
-    if (X.kind) {
-      if (atomicExch(&R.claimR[X.w], st) != st) {
+    if (X.kind()) {
+      if (atomicExch(&R.claimR[X.w()], st) != st) {
         bits |= 2u;
-        nR += R.cntR[X.w];
+        nR += R.cntR[X.w()];
       }
-      if (atomicExch(&R.claimL[X.w], st) != st) {
+      if (atomicExch(&R.claimL[X.w()], st) != st) {
         bits |= 8u;
-        nL += R.cntL[X.w];
+        nL += R.cntL[X.w()];
       }
     }
     R.aR[c] = nR;
@@ -457,9 +466,10 @@ __global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
   const int E = R.ctr[kCtrEvents];
-  // capacities: 4n entries per side (at most 2 per child event, 2n events),
-  // 2n touched lists (one per point and side)
-  const int64_t ent_cap = 2 * (int64_t)P.ecap, touched_cap = P.ecap;
+  // capacities: 3n entries per side (one per child event, 2n events, and one
+  // more per insertion, n of them: a point is inserted at most once in its
+  // block's movie), 2n touched lists (one per point and side)
+  const int64_t ent_cap = P.ecap + P.ecap / 2, touched_cap = P.ecap;
   if (R.aR[E] > ent_cap || R.aL[E] > ent_cap || R.aT[E] > touched_cap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
     return;
@@ -479,8 +489,8 @@ __global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
       R.touched[bT++] = X.a << 1;
     }
     if (bits & 2u) {
-      R.offR[X.w] = bR;
-      R.touched[bT++] = X.w << 1;
+      R.offR[X.w()] = bR;
+      R.touched[bT++] = X.w() << 1;
     }
     if (bits & 4u) {
       R.offL[X.b] = bL;
@@ -488,29 +498,34 @@ __global__ void __launch_bounds__(256) k_par_place(ParLevel P) {
       R.touched[bT++] = (X.b << 1) | 1;
     }
     if (bits & 8u) {
-      R.offL[X.w] = bL;
-      R.touched[bT++] = (X.w << 1) | 1;
+      R.offL[X.w()] = bL;
+      R.touched[bT++] = (X.w() << 1) | 1;
     }
   }
 }
 
-// Lists of link changes: every entry is the child event itself (its kind
-// field also carries its slot, kind | slot << 1, the sort key) and its time.
+// Lists of link changes: every entry is the child event and its slot in the
+// input movies (the sort key: a movie is in time order).
 __global__ void __launch_bounds__(256) k_par_fill(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts || P.h->err) return;  // after an error the offsets may be stale
   GRID_STRIDE(c, R.ctr[kCtrEvents]) {
     const int q = R.cslot[c];
     const Event E = R.ev_in[q];
-    const Event X{E.a, E.w, E.b, (q << 1) | E.kind, E.t, 0.0};
+    Entry X;
+    X.a = E.a;
+    X.wk = E.wk;
+    X.b = E.b;
+    X.key = q;
     int j = R.offR[E.a] + atomicAdd(&R.curR[E.a], 1);
     R.entR[j] = X;
     j = R.offL[E.b] + atomicAdd(&R.curL[E.b], 1);
     R.entL[j] = X;
-    if (E.kind) {
-      j = R.offR[E.w] + atomicAdd(&R.curR[E.w], 1);
+    if (E.kind()) {
+      const int w = E.w();
+      j = R.offR[w] + atomicAdd(&R.curR[w], 1);
       R.entR[j] = X;
-      j = R.offL[E.w] + atomicAdd(&R.curL[E.w], 1);
+      j = R.offL[w] + atomicAdd(&R.curL[w], 1);
       R.entL[j] = X;
     }
   }
@@ -521,29 +536,14 @@ __global__ void __launch_bounds__(256) k_par_sort(ParLevel P) {
   if (!R.pts || P.h->err) return;
   GRID_STRIDE(t, R.ctr[kCtrTouched]) {
     const int x = R.touched[t], p = x >> 1;
-    if (x & 1) sort_entries(R.entL + R.offL[p], R.cntL[p]);
-    else sort_entries(R.entR + R.offR[p], R.cntR[p]);
-  }
-}
-
-// Per segment: its merge and the slot of the child event it starts after.
-__global__ void __launch_bounds__(256) k_par_segtable(ParLevel P) {
-  const ParRun& R = P.run[blockIdx.y];
-  if (!R.pts) return;
-  const int merges = R.ctr[kCtrMerges];
-  const int64_t half = int64_t(1) << (P.k - 1);
-  const bool err = P.h->err != 0;
-  GRID_STRIDE(t, R.ctr[kCtrSegments]) {
-    const int g = find_owner(R.segBase, merges, t);
-    R.segMerge[t] = g;
-    const int i = (int)(t - R.segBase[g]);
-    const int64_t s = P.S.mlist[g].x;
-    R.segB[t] = i == 0 || err ? -1 : (int)boundary_slot(R, s, s + half, i, R.segS[g]);
+    if (x & 1) sort_entries(R.entL + R.offL[p], R.cntL[p], R.ev_in);
+    else sort_entries(R.entR + R.offR[p], R.cntR[p], R.ev_in);
   }
 }
 
 // Pass 1 counts each segment's bridge events; pass 2 writes them at their
 // place in the merge's bridge list.
+template <class PT>
 __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
       continue;
     }
     if (!write) {
-      R.segCnt[t] = walk_segment(R, P.h, s, m, e, b0, b1, nullptr, nullptr, 0,
+      R.segCnt[t] = walk_segment<PT>(R, P.h, s, m, e, b0, b1, nullptr, nullptr, 0,
                                  i == 0 ? &R.uv0[g] : nullptr, &R.segUV[t], false,
                                  R.segTmp + (int64_t)t * kSegKeep,
                                  R.segTmpUV + (int64_t)t * kSegKeep);
@@ -592,13 +592,14 @@ __global__ void __launch_bounds__(64) k_par_walk(ParLevel P, int write) {
     }
     if (cnt <= kSegKeep) continue;
     const int64_t last = (int64_t)t * kSegKeep + kSegKeep - 1;
-    walk_segment(R, P.h, s, m, e, b0, b1, R.bev + 2 * s + off + kSegKeep,
+    walk_segment<PT>(R, P.h, s, m, e, b0, b1, R.bev + 2 * s + off + kSegKeep,
                  R.buv + 2 * s + off + kSegKeep, cap - kSegKeep, nullptr, &R.segTmpUV[last],
                  true, nullptr, nullptr, &R.segTmp[last]);
   }
 }
 
 // Survival of every child event, and the number of bridge events before it.
+template <class PT>
 __global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
@@ -615,7 +616,7 @@ __global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
     const int64_t s = P.S.mlist[g].x, m = s + half;
     const bool isL = q < 2 * m;
     const Cand x = cand_of(R.ev_in, q);
-    const int j = count_before(R.pts, R.bev, 2 * s, R.nB[g], x, R.zs);
+    const int j = count_before((const PT*)R.pts, R.bev, 2 * s, R.nB[g], x, R.zs);
     const int2 ref = j > 0 ? R.buv[2 * s + j - 1] : R.uv0[g];
     R.surv[c] = isL ? (x.t.w < ref.x) : (x.t.w > ref.y);
     R.jb[c] = j;
@@ -625,7 +626,9 @@ __global__ void __launch_bounds__(256) k_par_classify(ParLevel P) {
 // Scatter: child survivors, then bridge events, to their places in the
 // merged movies; then every merge writes its length and splices its -inf
 // chains (no kernel of this level reads the -inf links after the walk).
+template <class PT>
 __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
+  const PT* pts = (const PT*)P.run[blockIdx.y].pts;
   const ParRun& R = P.run[blockIdx.y];
   if (!R.pts) return;
   const bool err = P.h->err != 0;
@@ -644,10 +647,10 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
       const Cand x = cand_of(R.ev_in, q);
       int64_t pos;
       if (q < 2 * m) {
-        const int idx = count_before(R.pts, R.ev_in, 2 * m, nR, x, R.zs);
+        const int idx = count_before(pts, R.ev_in, 2 * m, nR, x, R.zs);
         pos = (R.pre[c] - R.pre[c0]) + (R.pre[cR + idx] - R.pre[cR]) + R.jb[c];
       } else {
-        const int idx = count_before(R.pts, R.ev_in, 2 * s, nL, x, R.zs);
+        const int idx = count_before(pts, R.ev_in, 2 * s, nL, x, R.zs);
         pos = (R.pre[c0 + idx] - R.pre[c0]) + (R.pre[c] - R.pre[cR]) + R.jb[c];
       }
       if (pos >= 2 * (e - s)) {
@@ -665,8 +668,8 @@ __global__ void __launch_bounds__(256) k_par_scatter(ParLevel P) {
       const int nL = R.len_in[s], nR = R.len_in[m];
       const int c0 = R.eoff[g], cR = c0 + nL;
       const Cand x = cand_of(R.bev, 2 * s + j);
-      const int iL = count_before(R.pts, R.ev_in, 2 * s, nL, x, R.zs);
-      const int iR = count_before(R.pts, R.ev_in, 2 * m, nR, x, R.zs);
+      const int iL = count_before(pts, R.ev_in, 2 * s, nL, x, R.zs);
+      const int iR = count_before(pts, R.ev_in, 2 * m, nR, x, R.zs);
       const int64_t pos = j + (R.pre[c0 + iL] - R.pre[c0]) + (R.pre[cR + iR] - R.pre[cR]);
       if (pos >= 2 * (e - s)) {
         atomicCAS(&P.h->err, 0, HULL_EINTERNAL);
@@ -700,14 +703,18 @@ static ScanJobs jobs_of(const ParLevel& P, std::initializer_list<int> fields, in
     for (int f : fields) {
       int32_t* a = nullptr;
       switch (f) {
-        case 0: J.j[J.count] = ScanJob{R.ecnt, R.eoff, R.ctr + ctr_index}; break;
-        case 1: J.j[J.count] = ScanJob{R.segS, R.segBase, R.ctr + ctr_index}; break;
-        case 2: a = R.aR; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index}; break;
-        case 3: a = R.aL; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index}; break;
-        case 4: a = R.aT; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index}; break;
-        case 5: J.j[J.count] = ScanJob{R.segCnt, R.segOff, R.ctr + ctr_index}; break;
-        case 6: J.j[J.count] = ScanJob{R.nB, R.boff, R.ctr + ctr_index}; break;
-        default: J.j[J.count] = ScanJob{R.surv, R.pre, R.ctr + ctr_index}; break;
+        // the level totals of child events, walk segments and bridge events
+        // come from the scans themselves
+        case 0: J.j[J.count] = ScanJob{R.ecnt, R.eoff, R.ctr + ctr_index, R.ctr + kCtrEvents}; break;
+        case 1:
+          J.j[J.count] = ScanJob{R.segS, R.segBase, R.ctr + ctr_index, R.ctr + kCtrSegments};
+          break;
+        case 2: a = R.aR; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index, nullptr}; break;
+        case 3: a = R.aL; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index, nullptr}; break;
+        case 4: a = R.aT; J.j[J.count] = ScanJob{a, a, R.ctr + ctr_index, nullptr}; break;
+        case 5: J.j[J.count] = ScanJob{R.segCnt, R.segOff, R.ctr + ctr_index, nullptr}; break;
+        case 6: J.j[J.count] = ScanJob{R.nB, R.boff, R.ctr + ctr_index, R.ctr + kCtrBridge}; break;
+        default: J.j[J.count] = ScanJob{R.surv, R.pre, R.ctr + ctr_index, nullptr}; break;
       }
       ++J.count;
     }
@@ -715,14 +722,14 @@ static ScanJobs jobs_of(const ParLevel& P, std::initializer_list<int> fields, in
   return J;
 }
 
+template <class PT>
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   const dim3 g2(kStrideBlocks, 2), b256(256);
   hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
   // per merge: child events, walk segments (length: merges + 1)
   int32_t rc = exclusive_scan_dev_multi(jobs_of(P, {0, 1}, kCtrMerges), 1, P.S.mcap + 1, partials, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_par_totals, dim3(1, 2), dim3(64), 0, s, P);
-  hipLaunchKernelGGL(k_par_enum, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_enum<PT>, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_count, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_claim, g2, b256, 0, s, P);
   // per child event: list entries and lists it allocates (length: events + 1)
@@ -731,21 +738,22 @@ int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   hipLaunchKernelGGL(k_par_place, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_fill, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_sort, g2, b256, 0, s, P);
-  hipLaunchKernelGGL(k_par_segtable, g2, b256, 0, s, P);
   const dim3 gw(16384, 2), b64(64);
-  hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 0);
+  hipLaunchKernelGGL(k_par_walk<PT>, gw, b64, 0, s, P, 0);
   rc = exclusive_scan_dev_multi(jobs_of(P, {5}, kCtrSegments), 1, P.seg_cap + 1, partials, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_par_walk, gw, b64, 0, s, P, 1);
+  hipLaunchKernelGGL(k_par_walk<PT>, gw, b64, 0, s, P, 1);
   rc = exclusive_scan_dev_multi(jobs_of(P, {6}, kCtrMerges), 1, P.S.mcap + 1, partials, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_par_btotal, dim3(1, 2), dim3(64), 0, s, P);
-  hipLaunchKernelGGL(k_par_classify, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_classify<PT>, g2, b256, 0, s, P);
   rc = exclusive_scan_dev_multi(jobs_of(P, {7}, kCtrEvents), 1, P.ecap + 1, partials, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_par_scatter, g2, b256, 0, s, P);
+  hipLaunchKernelGGL(k_par_scatter<PT>, g2, b256, 0, s, P);
   HULL_LAUNCH_CHECK();
   return HULL_OK;
 }
+
+template int32_t parallel_level<int4>(const ParLevel&, int32_t*, hipStream_t);
+template int32_t parallel_level<WPt>(const ParLevel&, int32_t*, hipStream_t);
 
 }  // namespace hull

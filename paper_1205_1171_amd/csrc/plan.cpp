@@ -13,7 +13,7 @@ static int64_t scan_partials_needed(int64_t len) { return (len + kScanBlock - 1)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Plan make_plan(int64_t n, int64_t H, int min_seg) {
+Plan make_plan(int64_t n, int64_t H, int min_seg, int pt_bytes) {
   Plan p{};
   const int64_t nn = n > 0 ? n : 1;
   const int64_t hh = H > 0 ? H : 1;
@@ -34,14 +34,8 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     return o;
   };
   p.header = take(sizeof(Header));
-  p.keys0 = take(nn * 4);
-  p.vals0 = take(nn * 4);
-  p.keys1 = take(nn * 4);
-  p.vals1 = take(nn * 4);
-  p.counts = take(p.count_len * 4);
   p.partials = take(p.partial_len * 4);
-  p.pts = take(nn * sizeof(int4));
-  p.hid = take(nn * 4);
+  p.pts = take(nn * (size_t)pt_bytes);
   p.off1 = take(2 * sizeof(int64_t));
   p.mcnt = take((hh + 1) * 4);
   p.moff = take((hh + 1) * 4);
@@ -70,8 +64,25 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.curL[r] = take(nn * 4);
     p.claimR[r] = take(nn * 4);
     p.claimL[r] = take(nn * 4);
-    p.entR[r] = take(4 * nn * sizeof(Event));
-    p.entL[r] = take(4 * nn * sizeof(Event));
+    p.entR[r] = take(3 * nn * sizeof(Entry));
+    if (r == 0) {
+      // the sort's buffers live only until the points are gathered, before
+      // any merge: they share run 0's entry lists (48 bytes per point)
+      size_t o = p.entR[0];
+      auto sub = [&](size_t bytes) {
+        size_t q = o;
+        o = align256(o + bytes);
+        return q;
+      };
+      p.keys0 = sub(nn * 4);
+      p.vals0 = sub(nn * 4);
+      p.keys1 = sub(nn * 4);
+      p.vals1 = sub(nn * 4);
+      p.hid = sub(nn * 4);
+      p.counts = sub(p.count_len * 4);
+      static_assert(3 * sizeof(Entry) >= 20, "sort buffers must fit in the entry lists");
+    }
+    p.entL[r] = take(3 * nn * sizeof(Entry));
     p.ctr[r] = take(kCtrSlots * sizeof(int32_t));
     p.touched[r] = take(2 * nn * 4);
     p.ecnt[r] = take((p.mcap + 1) * 4);
@@ -92,12 +103,14 @@ Plan make_plan(int64_t n, int64_t H, int min_seg) {
     p.nB[r] = take((p.mcap + 1) * 4);
     p.boff[r] = take((p.mcap + 1) * 4);
     p.uv0[r] = take(p.mcap * sizeof(int2));
-    p.surv[r] = take((2 * nn + 1) * 4);
-    p.jb[r] = take(2 * nn * 4);
-    p.pre[r] = take((2 * nn + 1) * 4);
     p.aR[r] = take((2 * nn + 1) * 4);
     p.aL[r] = take((2 * nn + 1) * 4);
     p.aT[r] = take((2 * nn + 1) * 4);
+    // per-event survival flags and prefix sums are written after the list
+    // allocation counts are last read (place, before the walk): same space
+    p.surv[r] = p.aR[r];
+    p.jb[r] = p.aL[r];
+    p.pre[r] = p.aT[r];
     p.wf[r] = take(2 * nn);
   }
   p.total = off;

@@ -16,13 +16,16 @@
 // sign(tau_A - tau_B) = sign(N_A D_B - N_B D_A) sign(D_A) sign(D_B), whose
 // 12 epsilon coefficients are taken in decreasing order of size.
 //
-// Fast path: the "standard part" of tau (its real limit as e -> 0) in double,
-// stored with every event.  Two standard parts that differ by more than a
-// proven rounding bound decide the order; anything closer, equal, infinite on
-// both sides or not covered goes to the exact cascade (int128, then 256-bit).
+// Fast path: the "standard part" of tau (its real limit as e -> 0), computed
+// in double and stored with every event rounded to float.  Two standard parts
+// that differ by more than a proven rounding bound decide the order; anything
+// closer, equal, infinite on both sides or not covered goes to the exact
+// cascade (int128, then 256-bit).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "common.hpp"
 
 namespace hull {
 
@@ -32,6 +35,43 @@ typedef unsigned __int128 u128;
 struct Tri {
   int a, w, b;  // ranks, a < w < b
 };
+
+// A point of the wide coordinate range, |x|, |y| <= 2^30 and |z| <= 2^42 (the
+// lifted points of a Delaunay triangulation, float input on a 30-bit
+// lattice); w is the index within the hull, as in the int4 (x, y, z, w) of
+// the standard range.
+struct __align__(16) WPt {
+  int x, y, w, pad;
+  long long z;
+  long long pad2;
+};
+
+// Range of each coordinate: int32 rows, |c| <= 2^29; int64 rows (the wide
+// range), |x|, |y| <= 2^30 and |z| <= 2^42.
+__device__ __forceinline__ bool pt_out_of_range(int32_t x, int32_t y, int32_t z) {
+  return (x > kMaxCoord) | (x < -kMaxCoord) | (y > kMaxCoord) | (y < -kMaxCoord) |
+         (z > kMaxCoord) | (z < -kMaxCoord);
+}
+__device__ __forceinline__ bool pt_out_of_range(int64_t x, int64_t y, int64_t z) {
+  return (x > kMaxWideXY) | (x < -kMaxWideXY) | (y > kMaxWideXY) | (y < -kMaxWideXY) |
+         (z > kMaxWideZ) | (z < -kMaxWideZ);
+}
+
+// A point by rank: int4 (x, y, z, index within the hull) from int32 rows, WPt
+// from int64 rows (x and y of a row in range fit int32).
+__device__ __forceinline__ int4 make_pt(const int32_t* xyz, int64_t i, int local) {
+  return make_int4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], local);
+}
+__device__ __forceinline__ WPt make_pt(const int64_t* xyz, int64_t i, int local) {
+  WPt q;
+  q.x = (int)xyz[3 * i];
+  q.y = (int)xyz[3 * i + 1];
+  q.w = local;
+  q.pad = 0;
+  q.z = xyz[3 * i + 2];
+  q.pad2 = 0;
+  return q;
+}
 
 // ---------------------------------------------------------------------------
 // 256-bit signed accumulator: value = hi * 2^128 + lo (lo unsigned).
@@ -101,7 +141,10 @@ struct Coef {
   int dsign;  // sign of the perturbed D (never 0 for distinct indices)
 };
 
-__device__ __noinline__ void coef_of(int4 P, int4 Q, int4 R, int zs, Coef& c) {
+// Both point types: every difference fits int64 (|dx|, |dy| <= 2^31, |dz| <=
+// 2^43) and every coefficient int128 (at most 2^110 on the wide range).
+template <class PT>
+__device__ __noinline__ void coef_of(PT P, PT Q, PT R, int zs, Coef& c) {
   int64_t dx1 = (int64_t)Q.x - P.x, dx2 = (int64_t)R.x - P.x;
   int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
   int64_t dz1 = (int64_t)Q.z - P.z, dz2 = (int64_t)R.z - P.z;
@@ -187,14 +230,58 @@ __device__ __forceinline__ double tau_std(int4 P, int4 Q, int4 R, int zs) {
   return (double)(zs * N1) / (double)D1;
 }
 
+// Correctly rounded conversion of an int128 below 2^127 in magnitude: the
+// top 64 bits with a sticky bit for the rest, converted once (the bits below
+// the double's rounding position only decide "above half" versus "exactly
+// half", and the sticky bit keeps that), then scaled exactly.
+__device__ __forceinline__ double to_double(i128 v) {
+  const bool neg = v < 0;
+  const u128 u = neg ? (u128)(-v) : (u128)v;
+  const uint64_t hi = (uint64_t)(u >> 64);
+  double r;
+  if (hi == 0) {
+    r = (double)(uint64_t)u;
+  } else {
+    const int sh = 64 - __builtin_clzll(hi);
+    uint64_t t = (uint64_t)(u >> sh);
+    if ((u << (128 - sh)) != 0) t |= 1;
+    r = ldexp((double)t, sh);
+  }
+  return neg ? -r : r;
+}
+
+// Standard part of tau on the wide range: D0 fits int128 (up to 2^63), N0 up
+// to 2^75, D1 int64 (up to 2^58), N1 up to 2^70; each converted once
+// (correctly rounded) and divided once, so the filter bound below holds as
+// on the standard range.
+__device__ __forceinline__ double tau_std(const WPt& P, const WPt& Q, const WPt& R, int zs) {
+  const int64_t dx1 = (int64_t)Q.x - P.x, dx2 = (int64_t)R.x - P.x;
+  const int64_t dy1 = (int64_t)Q.y - P.y, dy2 = (int64_t)R.y - P.y;
+  const int64_t dz1 = Q.z - P.z, dz2 = R.z - P.z;
+  const i128 D0 = (i128)dx1 * dy2 - (i128)dx2 * dy1;
+  const i128 N0 = (i128)dx1 * dz2 - (i128)dx2 * dz1;
+  if (D0 != 0) return to_double(zs * N0) / to_double(D0);
+  if (N0 != 0) return __builtin_nan("");
+  const int64_t di1 = Q.w - P.w, di2 = R.w - P.w;
+  const int64_t D1 = di1 * dy2 - di2 * dy1;
+  if (D1 == 0) return __builtin_nan("");
+  const i128 N1 = (i128)di1 * dz2 - (i128)di2 * dz1;
+  return to_double(zs * N1) / to_double(D1);
+}
+
 // Does the standard-part filter decide sign(tau_A - tau_B)?  Each standard
-// part is a quotient of two integers below 2^62, each rounded once to double
-// and divided once: relative error at most 3 * 2^-53 (1 + 2^-52).  A gap
-// larger than 2^-50 (|sa| + |sb|) therefore fixes the sign.
+// part is a quotient of two integers below 2^76, each rounded once to double
+// and divided once (relative error at most 3 * 2^-53 (1 + 2^-52)), and the
+// value stored with an event is that double rounded once more to float
+// (2^-24 more): the error of either kind is below 2^-24 + 2^-51 relative,
+// and the quotients stay inside float's normal range (between 2^-76 and
+// 2^76 in magnitude).  A gap larger than 2^-23 (|sa| + |sb|) therefore fixes
+// the sign; the subtraction of two such values is exact or rounds by at most
+// 2^-53 relative, which the margin covers.
 __device__ __forceinline__ int std_cmp(double sa, double sb) {
   if (!(sa == sa) || !(sb == sb)) return 0;  // NaN: not covered
   double d = sa - sb;
-  double tol = 0x1p-50 * (fabs(sa) + fabs(sb));
+  double tol = 0x1p-23 * (fabs(sa) + fabs(sb));
   if (d > tol) return 1;
   if (-d > tol) return -1;
   return 0;

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "predicates.hpp"
 
 namespace hull {
 
@@ -22,17 +23,20 @@ __global__ void k_header_init(Header* h) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_extent(const int32_t* __restrict__ xyz, int64_t n,
+template <class InT>
+__global__ void __launch_bounds__(256) k_extent(const InT* __restrict__ xyz, int64_t n,
                                                 Header* h) {
   __shared__ int smin[256], smax[256], sbad[256];
   int lo = 0x7fffffff, hi = -0x7fffffff - 1, bad = 0;
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
-    int x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
-    lo = min(lo, x);
-    hi = max(hi, x);
-    bad |= (x > kMaxCoord) | (x < -kMaxCoord) | (y > kMaxCoord) | (y < -kMaxCoord) |
-           (z > kMaxCoord) | (z < -kMaxCoord);
+    const InT x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
+    const bool b = pt_out_of_range(x, y, z);
+    // x of a row in range fits int32 on either range
+    const int xi = b ? 0 : (int)x;
+    lo = min(lo, xi);
+    hi = max(hi, xi);
+    bad |= b;
   }
   smin[threadIdx.x] = lo;
   smax[threadIdx.x] = hi;
@@ -80,7 +84,8 @@ __device__ __forceinline__ int x_passes(const Header* h) {
 }
 
 // Digit of element p for (kind, d): kind 0 = x digit d, kind 1 = hull digit d.
-__device__ __forceinline__ uint32_t radix_key(const int32_t* xyz, const RadixBufs& B,
+template <class InT>
+__device__ __forceinline__ uint32_t radix_key(const InT* xyz, const RadixBufs& B,
                                               const int32_t* hid, int64_t p, int e, int kind,
                                               int minx, int32_t* val) {
   if (kind == 0) {
@@ -96,8 +101,9 @@ __device__ __forceinline__ uint32_t radix_key(const int32_t* xyz, const RadixBuf
   return (uint32_t)hid[v];
 }
 
+template <class InT>
 __global__ void __launch_bounds__(kSortThreads)
-    k_radix_hist(const int32_t* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
+    k_radix_hist(const InT* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
                  int64_t n, int kind, int d, int tiles, int32_t* __restrict__ counts,
                  const Header* h) {
   const int xp = x_passes(h);
@@ -120,8 +126,9 @@ __global__ void __launch_bounds__(kSortThreads)
   counts[(int64_t)threadIdx.x * tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
+template <class InT>
 __global__ void __launch_bounds__(kSortThreads)
-    k_radix_scatter(const int32_t* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
+    k_radix_scatter(const InT* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
                     int64_t n, int kind, int d, int tiles, const int32_t* __restrict__ offsets,
                     const Header* h) {
   const int xp = x_passes(h);
@@ -188,10 +195,11 @@ __global__ void __launch_bounds__(256) k_hull_ids(const int64_t* __restrict__ of
 }
 
 // Gather the points in rank order from the buffer of the last executed pass;
-// the fourth component is the index within the point's hull.
+// the index carried with each is the one within the point's hull.
+template <class InT, class PT>
 __global__ void __launch_bounds__(256)
-    k_gather(const int32_t* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
-             const int64_t* __restrict__ off, int hull_passes, int64_t n, int4* __restrict__ pts,
+    k_gather(const InT* __restrict__ xyz, RadixBufs B, const int32_t* __restrict__ hid,
+             const int64_t* __restrict__ off, int hull_passes, int64_t n, PT* __restrict__ pts,
              const Header* h) {
   const int e = x_passes(h) + hull_passes - 1;
   const int32_t* v = B.vals[e & 1];
@@ -199,7 +207,7 @@ __global__ void __launch_bounds__(256)
        r += (int64_t)gridDim.x * blockDim.x) {
     int i = v[r];
     int local = hid ? (int)(i - off[hid[i]]) : i;
-    pts[r] = make_int4(xyz[3 * (int64_t)i], xyz[3 * (int64_t)i + 1], xyz[3 * (int64_t)i + 2], local);
+    pts[r] = make_pt(xyz, i, local);
   }
 }
 
@@ -326,6 +334,8 @@ __global__ void __launch_bounds__(kSortThreads)
     if (q < nsums) sums[q] = carry + ex;
     carry += total;
   }
+  // the entries past *d_len (add of them) are zero: carry is the total
+  if (jb.total && threadIdx.x == 0) *jb.total = carry;
 }
 
 __global__ void __launch_bounds__(kSortThreads)
@@ -373,7 +383,7 @@ int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_
 int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
                            int64_t cap, int32_t* partials, hipStream_t s) {
   ScanJobs J{};
-  J.j[0] = ScanJob{in, out, d_len};
+  J.j[0] = ScanJob{in, out, d_len, nullptr};
   J.count = 1;
   return exclusive_scan_dev_multi(J, add, cap, partials, s);
 }
@@ -382,7 +392,8 @@ void init_header(Header* h, hipStream_t s) {
   hipLaunchKernelGGL(k_header_init, dim3(1), dim3(64), 0, s, h);
 }
 
-int32_t sort_points(const int32_t* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
+template <class InT, class PT>
+int32_t sort_points(const InT* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
                     const Plan& pl, hipStream_t s) {
   Header* h = (Header*)(ws + pl.header);
   RadixBufs B;
@@ -403,24 +414,29 @@ int32_t sort_points(const int32_t* d_xyz, int64_t n, const int64_t* hull_off, in
   const int tiles = (int)pl.tiles;
   unsigned eg = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
   if (eg < 1) eg = 1;
-  hipLaunchKernelGGL(k_extent, dim3(eg), dim3(256), 0, s, d_xyz, n, h);
+  hipLaunchKernelGGL(k_extent<InT>, dim3(eg), dim3(256), 0, s, d_xyz, n, h);
   hipLaunchKernelGGL(k_nbits, dim3(1), dim3(64), 0, s, h);
   if (hid) hipLaunchKernelGGL(k_hull_ids, dim3(eg), dim3(256), 0, s, hull_off, H, n, hid);
   for (int kind = 0; kind < 2; ++kind) {
     const int npass = kind == 0 ? 4 : hull_passes;
     for (int d = 0; d < npass; ++d) {
-      hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
+      hipLaunchKernelGGL(k_radix_hist<InT>, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
                          kind, d, tiles, counts, h);
       int32_t rc = exclusive_scan_i32(counts, counts, pl.count_len, partials, s);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
+      hipLaunchKernelGGL(k_radix_scatter<InT>, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
                          kind, d, tiles, counts, h);
     }
   }
-  hipLaunchKernelGGL(k_gather, dim3(eg), dim3(256), 0, s, d_xyz, B, hid, hull_off, hull_passes, n,
-                     (int4*)(ws + pl.pts), h);
+  hipLaunchKernelGGL((k_gather<InT, PT>), dim3(eg), dim3(256), 0, s, d_xyz, B, hid, hull_off,
+                     hull_passes, n, (PT*)(ws + pl.pts), h);
   HULL_LAUNCH_CHECK();
   return HULL_OK;
 }
+
+template int32_t sort_points<int32_t, int4>(const int32_t*, int64_t, const int64_t*, int64_t,
+                                            char*, const Plan&, hipStream_t);
+template int32_t sort_points<int64_t, WPt>(const int64_t*, int64_t, const int64_t*, int64_t,
+                                           char*, const Plan&, hipStream_t);
 
 }  // namespace hull

@@ -23,10 +23,10 @@ _lib = None
 class Schedule(ctypes.Structure):
     """hull_schedule_t: merge schedule of a batched call (-1 / 0 = default)."""
     _fields_ = [("serial_levels", ctypes.c_int32), ("walk_segment", ctypes.c_int32),
-                ("fused_levels", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fused_levels", ctypes.c_int32), ("wave_from", ctypes.c_int32)]
 
-    def __init__(self, serial_levels=-1, walk_segment=0, fused_levels=-1):
-        super().__init__(int(serial_levels), int(walk_segment), int(fused_levels), 0)
+    def __init__(self, serial_levels=-1, walk_segment=0, fused_levels=-1, wave_from=0):
+        super().__init__(int(serial_levels), int(walk_segment), int(fused_levels), int(wave_from))
 
 
 class HullError(RuntimeError):
@@ -67,6 +67,12 @@ def lib():
     for f in (L.hull_lower, L.hull_full):
         f.argtypes = [P, i64, P, i64, P, P, sz, P]
         f.restype = i32
+    for f in (L.hull_lower_wide, L.hull_full_wide):
+        f.argtypes = [P, i64, P, i64, P, P, sz, P]
+        f.restype = i32
+    for f in (L.hull_lower_f32, L.hull_full_f32):
+        f.argtypes = [P, i64, i32, P, i64, P, P, sz, P]
+        f.restype = i32
     L.hull_full_timed.argtypes = [P, i64, P, i64, P, P, sz, P, P, i32]
     L.hull_full_timed.restype = i32
     L.hull_workspace_bytes_batched.argtypes = [i64, i64, ctypes.POINTER(sz)]
@@ -97,6 +103,7 @@ def exported_symbols():
     """Names declared in include/hull3d.h that the library exports."""
     L = lib()
     names = ["hull_strerror", "hull_last_hip_error", "hull_workspace_bytes", "hull_lower", "hull_full", "hull_full_timed",
+             "hull_lower_wide", "hull_full_wide", "hull_lower_f32", "hull_full_f32",
              "hull_workspace_bytes_batched", "hull_full_batched", "hull_schedule_defaults",
              "hull_movies", "hull_adjacency_workspace_bytes", "hull_face_adjacency",
              "hull_delaunay_workspace_bytes", "hull_delaunay",
@@ -104,7 +111,10 @@ def exported_symbols():
     return [n for n in names if hasattr(L, n)]
 
 
-def workspace_bytes(n, flags=0):
+WS_STANDARD, WS_WIDE, WS_F32 = 0, 1, 2
+
+
+def workspace_bytes(n, flags=WS_STANDARD):
     out = ctypes.c_size_t(0)
     rc = lib().hull_workspace_bytes(int(n), int(flags), ctypes.byref(out))
     if rc:
@@ -206,6 +216,61 @@ def hull_sync(xyz, lower_only=False, ws=None):
     return faces[:F]
 
 
+def hull_wide(xyz, lower_only=False, ws=None, stream=None):
+    """Blocking hull of int64 points [n, 3] on the wide range (|x|, |y| <=
+    2^30, |z| <= 2^42): the face tensor [F, 3] on the device."""
+    import torch
+    if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.int64):
+        raise TypeError("points must be a CUDA int64 tensor")
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or not xyz.is_contiguous():
+        raise ValueError("points must be a contiguous [n, 3] tensor")
+    with _on(stream):
+        n = xyz.shape[0]
+        dev = xyz.device
+        cap = max(2 * n, 1)
+        faces = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        info = torch.empty(2, dtype=torch.int64, device=dev)
+        wbuf = (ws or Workspace()).get(workspace_bytes(n, WS_WIDE), dev)
+        fn = lib().hull_lower_wide if lower_only else lib().hull_full_wide
+        rc = fn(ctypes.c_void_p(xyz.data_ptr()), n, ctypes.c_void_p(faces.data_ptr()), cap,
+                ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(),
+                _stream(None))
+        if rc:
+            raise HullError(rc, "hull_lower_wide" if lower_only else "hull_full_wide")
+        st, F = (int(v) for v in info.cpu())
+    if st:
+        raise HullError(st, "device")
+    return faces[:F]
+
+
+def hull_f32(p, bits=30, lower_only=False, ws=None, stream=None):
+    """Blocking hull of float32 points [n, 3] snapped to the lattice of
+    ``bits`` bits (scale 2^(bits - E), E the least integer with max |c| <=
+    2^E; round to nearest, ties to even): the face tensor [F, 3]."""
+    import torch
+    if not (isinstance(p, torch.Tensor) and p.is_cuda and p.dtype == torch.float32):
+        raise TypeError("points must be a CUDA float32 tensor")
+    if p.dim() != 2 or p.shape[1] != 3 or not p.is_contiguous():
+        raise ValueError("points must be a contiguous [n, 3] tensor")
+    with _on(stream):
+        n = p.shape[0]
+        dev = p.device
+        cap = max(2 * n, 1)
+        faces = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        info = torch.empty(2, dtype=torch.int64, device=dev)
+        wbuf = (ws or Workspace()).get(workspace_bytes(n, WS_F32), dev)
+        fn = lib().hull_lower_f32 if lower_only else lib().hull_full_f32
+        rc = fn(ctypes.c_void_p(p.data_ptr()), n, int(bits), ctypes.c_void_p(faces.data_ptr()),
+                cap, ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()),
+                wbuf.numel(), _stream(None))
+        if rc:
+            raise HullError(rc, "hull_lower_f32" if lower_only else "hull_full_f32")
+        st, F = (int(v) for v in info.cpu())
+    if st:
+        raise HullError(st, "device")
+    return faces[:F]
+
+
 def hull_batched(xyz, offsets, schedule=None, ws=None, faces=None, stream=None):
     """Full hulls of H clouds in one call: cloud h is rows [offsets[h],
     offsets[h+1]) of ``xyz``.  Returns (faces [cap, 3], face_offsets [H + 1],
@@ -257,6 +322,11 @@ def face_adjacency(faces, face_off=None, pt_off=None, ws=None, stream=None):
     """Half-edge twins of face rows (device int32 [F, 3] -> device int32
     [F, 3]); face_off / pt_off: device int64 [H + 1] for a batch (vertex
     indices within each cloud).  Blocking: returns (adj, open_edges)."""
+    with _on(stream):
+        return _face_adjacency(faces, face_off, pt_off, ws)
+
+
+def _face_adjacency(faces, face_off, pt_off, ws):
     import torch
     if not (isinstance(faces, torch.Tensor) and faces.is_cuda and faces.dtype == torch.int32):
         raise TypeError("faces must be a CUDA int32 tensor")
@@ -274,7 +344,7 @@ def face_adjacency(faces, face_off=None, pt_off=None, ws=None, stream=None):
     rc = lib().hull_face_adjacency(ctypes.c_void_p(faces.data_ptr()), F, _ptr(face_off),
                                    _ptr(pt_off), H, ctypes.c_void_p(adj.data_ptr()),
                                    ctypes.c_void_p(info.data_ptr()),
-                                   ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(), _stream(stream))
+                                   ctypes.c_void_p(wbuf.data_ptr()), wbuf.numel(), _stream(None))
     if rc:
         raise HullError(rc, "hull_face_adjacency")
     st, open_edges = (int(v) for v in info.cpu())
@@ -285,7 +355,12 @@ def face_adjacency(faces, face_off=None, pt_off=None, ws=None, stream=None):
 
 def delaunay(xy, ws=None, stream=None):
     """Delaunay triangles (device int32 [T, 3], counter-clockwise) of the
-    CUDA int32 points xy [n, 2], |x|, |y| <= 2^14.  Blocking (checked)."""
+    CUDA int32 points xy [n, 2], |x|, |y| <= 2^20.  Blocking (checked)."""
+    with _on(stream):
+        return _delaunay(xy, ws)
+
+
+def _delaunay(xy, ws):
     import torch
     if not (isinstance(xy, torch.Tensor) and xy.is_cuda and xy.dtype == torch.int32):
         raise TypeError("points must be a CUDA int32 tensor")
@@ -303,7 +378,7 @@ def delaunay(xy, ws=None, stream=None):
     wbuf = (ws or Workspace()).get(nb.value, dev)
     rc = lib().hull_delaunay(ctypes.c_void_p(xy.data_ptr()), n, ctypes.c_void_p(tris.data_ptr()), cap,
                              ctypes.c_void_p(info.data_ptr()), ctypes.c_void_p(wbuf.data_ptr()),
-                             wbuf.numel(), _stream(stream))
+                             wbuf.numel(), _stream(None))
     if rc:
         raise HullError(rc, "hull_delaunay")
     st, T = (int(v) for v in info.cpu())
@@ -360,10 +435,11 @@ def volume_area_fwd(p, pt_off, faces, face_off, stream=None):
     import torch
     _check_volume_args(p, pt_off, faces, face_off)
     H = pt_off.numel() - 1
-    V = torch.empty(H, dtype=torch.float32, device=p.device)
-    A = torch.empty(H, dtype=torch.float32, device=p.device)
-    rc = lib().hull_volume_area_fwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
-                                    _ptr(V), _ptr(A), _stream(stream))
+    with _on(stream):
+        V = torch.empty(H, dtype=torch.float32, device=p.device)
+        A = torch.empty(H, dtype=torch.float32, device=p.device)
+        rc = lib().hull_volume_area_fwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
+                                        _ptr(V), _ptr(A), _stream(None))
     if rc:
         raise HullError(rc, "hull_volume_area_fwd")
     return V, A
@@ -381,9 +457,10 @@ def volume_area_bwd(p, pt_off, faces, face_off, gV, gA, stream=None):
                                   and t.numel() == H and t.device == p.device):
             raise TypeError(f"{name} must be None or a contiguous CUDA float32 tensor of {H} "
                             "entries")
-    g = torch.empty_like(p)
-    rc = lib().hull_volume_area_bwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
-                                    _ptr(gV), _ptr(gA), _ptr(g), _stream(stream))
+    with _on(stream):
+        g = torch.empty_like(p)
+        rc = lib().hull_volume_area_bwd(_ptr(p), _ptr(pt_off), _ptr(faces), _ptr(face_off), H,
+                                        _ptr(gV), _ptr(gA), _ptr(g), _stream(None))
     if rc:
         raise HullError(rc, "hull_volume_area_bwd")
     return g

@@ -210,3 +210,35 @@ def planar(n=1 << 18):
             break
         p[d] = draw(rng, len(d))
     return np.ascontiguousarray(p.astype(np.int32))
+
+
+def planar_wide(n=1 << 18):
+    """Delaunay workload on the full lifting range: n distinct int32 points
+    uniform in [-2^20, 2^20]^2 (lifted z up to 2^41), [n, 2]."""
+    rng = rng_for(7)
+    draw = lambda r, k: r.integers(-R20, R20, size=(k, 2), endpoint=True)
+    p = draw(rng, n)
+    for _ in range(1000):
+        key = (p[:, 0] + 2 * R20) * (4 * R20 + 1) + (p[:, 1] + 2 * R20)
+        _, first = np.unique(key, return_index=True)
+        dup = np.ones(n, dtype=bool)
+        dup[first] = False
+        d = np.nonzero(dup)[0]
+        if len(d) == 0:
+            break
+        p[d] = draw(rng, len(d))
+    return np.ascontiguousarray(p.astype(np.int32))
+
+
+def float_ball(n=1 << 20):
+    """Float-input workload: n float32 points uniform in the unit ball
+    (rejection from the cube, in float64, then rounded to float32), [n, 3].
+    On the 30-bit lattice (scale 2^30, as the largest |c| is just below 1)
+    every coordinate of magnitude at least 2^-7 keeps its float32 value
+    exactly."""
+    rng = rng_for(8)
+    out = np.empty((0, 3))
+    while len(out) < n:
+        c = rng.uniform(-1.0, 1.0, size=(2 * n, 3))
+        out = np.concatenate([out, c[(c * c).sum(axis=1) <= 1.0]])
+    return np.ascontiguousarray(out[:n].astype(np.float32))

@@ -12,8 +12,11 @@ records, per cloud in cloud order, the oracle's face count, and the SHA-256
 of the concatenation of every cloud's canonical face array (indices local to
 the cloud).
 
-For the Delaunay workload (planar: 2^18 points in [-2^14, 2^14]^2) it
-records the SHA-256 of the oracle's canonical triangle array.
+For the Delaunay workloads (planar: 2^18 points in [-2^14, 2^14]^2;
+planar_wide: 2^18 points in [-2^20, 2^20]^2) it records the SHA-256 of the
+oracle's canonical triangle array; for the float-input workload (float_ball:
+2^20 float32 points in the unit ball, on the 30-bit lattice) the face count
+and the SHA-256 of the oracle's canonical faces (full and lower).
 
 For the differentiation workload cfg5 (256 clouds of 16,384 float32 points,
 hulls on their int32 lattice points) it records, per cloud, the oracle's face
@@ -23,6 +26,7 @@ faces), and the FP64 gradient of a seeded weighted loss sum_b wV[b] V_b +
 wA[b] A_b at 16 seeded vertices of every cloud.
 
 usage: python tests/golden/make_golden.py cfg1 cfg2_sphere cfg2_ball cfg3 cfg4 cfg5 planar
+       planar_wide float_ball
 (the lower and upper runs go to two processes; the clouds of cfg4 to a pool)
 """
 import hashlib
@@ -155,9 +159,9 @@ def make_cfg5(name, workers):
 
 
 def make_delaunay(name):
-    """The Delaunay workload: the oracle's lifted lower hull, CCW triangles."""
+    """A Delaunay workload: the oracle's lifted lower hull, CCW triangles."""
     from oracle import delaunay as dl
-    p = workloads.planar()
+    p = workloads.planar() if name == "planar" else workloads.planar_wide()
     t = time.time()
     tris = dl.delaunay(p)
     rec = {
@@ -173,9 +177,37 @@ def make_delaunay(name):
     print(name, rec["T"], rec["oracle_seconds"], flush=True)
 
 
+def make_float(name, bits=30):
+    """The float-input workload: the oracle's hull of the float32 points
+    snapped to the 30-bit lattice (lower and upper runs)."""
+    from oracle import floatin
+    p = workloads.float_ball()
+    t = time.time()
+    lower = floatin.hull_f32(p, bits, lower_only=True)
+    faces = floatin.hull_f32(p, bits)
+    rec = {
+        "config": name,
+        "n": int(len(p)),
+        "bits": bits,
+        "input_sha256": hashlib.sha256(np.ascontiguousarray(p, dtype="<f4").tobytes()).hexdigest(),
+        "F": int(len(faces)),
+        "F_lower": int(len(lower)),
+        "V": int(validate.vertex_count(faces)),
+        "euler_ok": bool(validate.euler_ok(faces)),
+        "sha256_full": digest(faces),
+        "sha256_lower": digest(lower),
+        "oracle_seconds": time.time() - t,
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(name, rec["F"], rec["V"], rec["oracle_seconds"], flush=True)
+
+
 def make(name):
-    if name == "planar":
+    if name in ("planar", "planar_wide"):
         return make_delaunay(name)
+    if name == "float_ball":
+        return make_float(name)
     if name == "cfg4":
         return make_batched(name, int(os.environ.get("GOLDEN_WORKERS", "6")))
     if name == "cfg5":

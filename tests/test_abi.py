@@ -152,11 +152,14 @@ def test_delaunay_argument_errors(L):
 def test_schedule_defaults(L, monkeypatch):
     """Built-in defaults, the environment overrides, and the number of
     LDS-staged levels reported in fused_levels."""
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL"):
         monkeypatch.delenv(k, raising=False)
     s = hull.schedule_defaults()
     assert (s.serial_levels, s.walk_segment) == (9, 4)
-    assert 0 <= s.fused_levels <= s.serial_levels and s.reserved == 0
+    assert 0 <= s.fused_levels <= s.serial_levels and s.wave_from == 0
+    monkeypatch.setenv("HULL_WAVE_LEVEL", "2")  # raised above the LDS-staged levels
+    assert hull.schedule_defaults().wave_from == s.fused_levels + 1
+    monkeypatch.delenv("HULL_WAVE_LEVEL")
     monkeypatch.setenv("HULL_SERIAL_LEVELS", "12")
     monkeypatch.setenv("HULL_WALK_SEGMENT", "32")
     s = hull.schedule_defaults()
@@ -176,3 +179,55 @@ def test_adjacency_face_limit(L):
     fake = P(0x1000)
     assert L.hull_face_adjacency(fake, fmax + 1, None, None, 1, fake, fake, fake, 1 << 40,
                                  None) == hull.HULL_EINVAL
+
+
+def test_workspace_kinds(L):
+    out = ctypes.c_size_t(0)
+    n = 100000
+    sizes = []
+    for flags in (hull.WS_STANDARD, hull.WS_WIDE, hull.WS_F32):
+        assert L.hull_workspace_bytes(n, flags, ctypes.byref(out)) == hull.HULL_OK
+        sizes.append(out.value)
+    # the wide points take 32 bytes instead of 16; the float entry adds its rows
+    assert sizes[1] >= sizes[0] + 16 * n and sizes[2] >= sizes[1] + 24 * n
+    for flags in (-1, 3, 77):
+        assert L.hull_workspace_bytes(n, flags, ctypes.byref(out)) == hull.HULL_EINVAL
+    assert L.hull_delaunay_workspace_bytes(n, ctypes.byref(out)) == hull.HULL_OK
+    assert out.value >= sizes[1] + 24 * n
+
+
+def test_wide_and_f32_argument_errors(L):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    info = P(0x2000)
+    out = ctypes.c_size_t(0)
+    L.hull_workspace_bytes(100, hull.WS_WIDE, ctypes.byref(out))
+    wsw = out.value
+    L.hull_workspace_bytes(100, hull.WS_F32, ctypes.byref(out))
+    wsf = out.value
+    for fn in (L.hull_lower_wide, L.hull_full_wide):
+        assert fn(None, 100, fake, 200, info, fake, wsw, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 199, info, fake, wsw, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 200, None, fake, wsw, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, fake, 200, info, fake, wsw - 1, None) == hull.HULL_EWORKSPACE
+        assert fn(fake, (1 << 26) + 1, fake, 1 << 28, info, fake, 1 << 40, None) == hull.HULL_EINVAL
+    for fn in (L.hull_lower_f32, L.hull_full_f32):
+        assert fn(fake, 100, 0, fake, 200, info, fake, wsf, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, 31, fake, 200, info, fake, wsf, None) == hull.HULL_EINVAL
+        assert fn(None, 100, 30, fake, 200, info, fake, wsf, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, 30, fake, 199, info, fake, wsf, None) == hull.HULL_EINVAL
+        assert fn(fake, 100, 30, fake, 200, info, fake, wsf - 1, None) == hull.HULL_EWORKSPACE
+
+
+def test_workspace_limits(L):
+    """Workspace per point stays below 1 KiB (n = 2^24 under 16 GiB); the
+    batch limit is 2^28 points, whose workspace fits 288 GB."""
+    out = ctypes.c_size_t(0)
+    n = 1 << 24
+    assert L.hull_workspace_bytes(n, 0, ctypes.byref(out)) == hull.HULL_OK
+    assert out.value < 1024 * n
+    assert L.hull_workspace_bytes_batched(1 << 28, 10000, ctypes.byref(out)) == hull.HULL_OK
+    assert out.value < 288e9
+    assert L.hull_workspace_bytes_batched((1 << 28) + 1, 10000, ctypes.byref(out)) == hull.HULL_EINVAL
+    assert L.hull_workspace_bytes((1 << 26), 0, ctypes.byref(out)) == hull.HULL_OK
+    assert out.value < 288e9

@@ -33,7 +33,7 @@ def H():
     from paper_1205_1171_amd import hull
     assert torch.cuda.is_available()
     hull.lib()
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL"):
         os.environ.pop(k, None)
     return hull
 
@@ -50,6 +50,7 @@ SCHEDULES = {
     "parallel": (0, 16, 0),
     "parallel_seg4": (0, 4, 0),
     "split3": (3, 32, 0),
+    "wave6": (14, 8, 0, 6),
 }
 
 

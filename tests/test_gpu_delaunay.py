@@ -51,7 +51,7 @@ def test_small_and_degenerate(H):
              np.array([[0, 0]] * 5 + [[4, 1], [2, 7]])]                    # duplicates
     for t in range(24):
         n = int(rng.integers(3, 2500))
-        r = [3, 50, 1 << 14][t % 3]
+        r = [3, 50, 1 << 14, 1 << 20][t % 4]
         cases.append(rng.integers(-r, r, size=(n, 2), endpoint=True))
     for t, p in enumerate(cases):
         say("delaunay case", t, len(p))
@@ -63,19 +63,41 @@ def test_small_and_degenerate(H):
 
 def test_range_error(H):
     import torch
-    p = np.array([[0, 0], [1 << 14, 0], [0, (1 << 14) + 1], [5, 5]], dtype=np.int32)
+    p = np.array([[0, 0], [1 << 20, 0], [0, (1 << 20) + 1], [5, 5]], dtype=np.int32)
     with pytest.raises(H.HullError) as e:
         H.delaunay(torch.from_numpy(p).cuda())
     assert e.value.code == H.HULL_ERANGE
-    p[2, 1] = -(1 << 14)
+    p[2, 1] = -(1 << 20)
+    assert same(gpu_tris(H, p), dl.delaunay(p))
+    p = np.array([[1 << 20, 1 << 20], [-(1 << 20), 1 << 20], [1 << 20, -(1 << 20)],
+                  [-(1 << 20), -(1 << 20)], [0, 0], [1, -1]], dtype=np.int32)
     assert same(gpu_tris(H, p), dl.delaunay(p))
 
 
-def test_full_size_digest(H):
-    rec = json.load(open(os.path.join(GOLDEN, "planar.json")))
-    p = workloads.planar()
+def test_wide_grid_and_circle(H):
+    """Cocircular and collinear ties at the full lifting range."""
+    rng = np.random.default_rng(13)
+    k = 1 << 17
+    grid = np.array([(x * k, y * k) for x in range(-8, 9) for y in range(-8, 9)])
+    ang = rng.integers(0, 1 << 16, size=400)
+    # lattice points near a circle of radius 2^20 - 1, many with the same lift
+    circ = np.unique(np.rint(((1 << 20) - 1) * np.column_stack(
+        [np.cos(ang * 2 * np.pi / (1 << 16)), np.sin(ang * 2 * np.pi / (1 << 16))])).astype(np.int64),
+        axis=0)
+    # twelve points on the circle of radius 5 * 2^17 (3-4-5 triangles), all cocircular
+    sym = np.array([(sx * a, sy * b) for a, b in ((3 << 17, 4 << 17), (4 << 17, 3 << 17), (5 << 17, 0),
+                                                  (0, 5 << 17)) for sx in (-1, 1) for sy in (-1, 1)])
+    for name, p in (("grid", grid), ("circle", circ), ("symmetric circle", np.unique(sym, axis=0))):
+        say("delaunay wide", name, len(p))
+        assert same(gpu_tris(H, p), dl.delaunay(p)), name
+
+
+@pytest.mark.parametrize("name", ["planar", "planar_wide"])
+def test_full_size_digest(H, name):
+    rec = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
+    p = getattr(workloads, name)()
     assert hashlib.sha256(np.ascontiguousarray(p, dtype="<i4").tobytes()).hexdigest() == rec["input_sha256"]
-    say("delaunay full size", len(p))
+    say("delaunay full size", name, len(p))
     t = gpu_tris(H, p)
     assert len(t) == rec["T"]
     assert hashlib.sha256(validate.canonical(t).astype("<i4").tobytes()).hexdigest() == rec["sha256"]

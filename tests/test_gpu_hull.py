@@ -44,13 +44,22 @@ def ws(H):
 # and scatter), and the default split between them.  All must give the same
 # movies and faces.  The parallel strategy is also run with walk segments of
 # 4 child events (the minimum), so that most walks start from a tangent found at a segment
-# boundary, and with a split after level 3.
+# boundary, and with a split after level 3.  The wave strategies run the
+# lane-serial levels from level 5 (or 7) up one merge per wavefront.
 STRATEGIES = {
-    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": ""},
-    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16"},
-    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4"},
-    "split3_seg64": {"HULL_SERIAL_LEVELS": "3", "HULL_WALK_SEGMENT": "64"},
-    "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": ""},
+    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": ""},
+    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16", "HULL_WAVE_LEVEL": ""},
+    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4", "HULL_WAVE_LEVEL": ""},
+    "split3_seg64": {"HULL_SERIAL_LEVELS": "3", "HULL_WALK_SEGMENT": "64", "HULL_WAVE_LEVEL": ""},
+    "wave5": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
+              "HULL_WAVE_LANES": "16"},
+    "wave5_8": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
+                "HULL_WAVE_LANES": "8"},
+    "wave5_64": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
+                 "HULL_WAVE_LANES": "64"},
+    "wave7_split10": {"HULL_SERIAL_LEVELS": "10", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "7",
+                      "HULL_WAVE_LANES": "32"},
+    "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": ""},
 }
 
 
@@ -196,7 +205,7 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
