@@ -138,20 +138,26 @@ int32_t hull_lower_f32(const float* d_xyz, int64_t n, int32_t bits, int32_t* d_f
  *   fused_levels   ignored on input (pass 0 or -1); hull_schedule_defaults
  *                  writes the number of LDS-staged lowest levels here
  *   wave_from      lane-serial levels from this one on run one merge per
- *                  wavefront instead of one per lane (the six candidates of
- *                  an iteration on six lanes, child movies through LDS); 0:
- *                  the default, negative: no level */
+ *                  group of wave_lanes lanes instead of one per lane (the
+ *                  six candidates of an iteration on six lanes, child movies
+ *                  through LDS); 0: the default, negative: no level
+ *   wave_lanes     lanes per merge at level wave_from: 8, 16, 32 or 64,
+ *                  doubling with every level above (merges halve), up to 64
+ *                  (0: the default, 8)
+ *   reserved       pass 0 */
 typedef struct hull_schedule_t {
   int32_t serial_levels;
   int32_t walk_segment;
   int32_t fused_levels;
   int32_t wave_from;
+  int32_t wave_lanes;
+  int32_t reserved;
 } hull_schedule_t;
 
 /* The schedule the library uses when a call passes none (or leaves a field
  * at its default): the built-in defaults, overridden by the environment
- * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT and HULL_WAVE_LEVEL when
- * set.  On output,
+ * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT, HULL_WAVE_LEVEL and
+ * HULL_WAVE_LANES when set.  On output,
  * fused_levels is the number of lowest lane-serial levels that stage each
  * merge's points and links in LDS (a separate kernel from the other
  * lane-serial levels).  Host, synchronous. */

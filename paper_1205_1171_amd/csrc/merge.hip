@@ -673,17 +673,17 @@ static int env_int(const char* name, int dflt) {
 struct Opts {
   int serial_max, seg;
   int wave_from;   // first lane-serial level run by lane groups (0: none)
-  int wave_lanes;  // lanes per merge there: 16, 32 or 64
+  int wave_lanes;  // lanes per merge at level wave_from (8, 16, 32 or 64), doubling per level
 };
 
 static Opts resolve(const hull_schedule_t* sc) {
   Opts o;
-  o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 9);
+  o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 10);
   o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 4);
   if (o.seg < kMinWalkSegment) o.seg = kMinWalkSegment;
-  const int wf = sc && sc->wave_from != 0 ? sc->wave_from : env_int("HULL_WAVE_LEVEL", 0);
+  const int wf = sc && sc->wave_from != 0 ? sc->wave_from : env_int("HULL_WAVE_LEVEL", 8);
   o.wave_from = wf > 0 ? std::max(wf, kLdsLevels + 1) : 0;
-  const int wl = env_int("HULL_WAVE_LANES", 16);
+  const int wl = sc && sc->wave_lanes > 0 ? sc->wave_lanes : env_int("HULL_WAVE_LANES", 8);
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
   return o;
 }
@@ -824,13 +824,14 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
         hipLaunchKernelGGL(k_work_place, grid, dim3(256), 0, s, B);
       }
       if (opt.wave_from > 0 && k >= opt.wave_from) {
-        const int per = 256 / opt.wave_lanes;  // merges per block
+        // lanes per merge double with every level (merges halve), so that
+        // every lane-group level keeps about the same number of waves
+        const int lanes = std::min(64, opt.wave_lanes << std::min(k - opt.wave_from, 3));
+        const int per = 256 / lanes;  // merges per block
         const dim3 wg((unsigned)((bound + per - 1) / per), 2);
-        if (opt.wave_lanes == 64) hipLaunchKernelGGL((k_merge_wave<PT, 64>), wg, dim3(256), 0, s, B);
-        else if (opt.wave_lanes == 32)
-          hipLaunchKernelGGL((k_merge_wave<PT, 32>), wg, dim3(256), 0, s, B);
-        else if (opt.wave_lanes == 16)
-          hipLaunchKernelGGL((k_merge_wave<PT, 16>), wg, dim3(256), 0, s, B);
+        if (lanes == 64) hipLaunchKernelGGL((k_merge_wave<PT, 64>), wg, dim3(256), 0, s, B);
+        else if (lanes == 32) hipLaunchKernelGGL((k_merge_wave<PT, 32>), wg, dim3(256), 0, s, B);
+        else if (lanes == 16) hipLaunchKernelGGL((k_merge_wave<PT, 16>), wg, dim3(256), 0, s, B);
         else hipLaunchKernelGGL((k_merge_wave<PT, 8>), wg, dim3(256), 0, s, B);
       } else
         hipLaunchKernelGGL(k_merge_level<PT>, grid, dim3(256), 0, s, B);
@@ -1040,6 +1041,8 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
   out->walk_segment = o.seg;
   out->fused_levels = hull::kLdsLevels;
   out->wave_from = o.wave_from;
+  out->wave_lanes = o.wave_lanes;
+  out->reserved = 0;
   return HULL_OK;
 }
 

@@ -152,14 +152,19 @@ def test_delaunay_argument_errors(L):
 def test_schedule_defaults(L, monkeypatch):
     """Built-in defaults, the environment overrides, and the number of
     LDS-staged levels reported in fused_levels."""
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES"):
         monkeypatch.delenv(k, raising=False)
     s = hull.schedule_defaults()
-    assert (s.serial_levels, s.walk_segment) == (9, 4)
-    assert 0 <= s.fused_levels <= s.serial_levels and s.wave_from == 0
+    assert (s.serial_levels, s.walk_segment, s.wave_from, s.wave_lanes) == (10, 4, 8, 8)
+    assert 0 <= s.fused_levels <= s.serial_levels
     monkeypatch.setenv("HULL_WAVE_LEVEL", "2")  # raised above the LDS-staged levels
     assert hull.schedule_defaults().wave_from == s.fused_levels + 1
+    monkeypatch.setenv("HULL_WAVE_LEVEL", "-1")
+    assert hull.schedule_defaults().wave_from == 0
     monkeypatch.delenv("HULL_WAVE_LEVEL")
+    monkeypatch.setenv("HULL_WAVE_LANES", "64")
+    assert hull.schedule_defaults().wave_lanes == 64
+    monkeypatch.delenv("HULL_WAVE_LANES")
     monkeypatch.setenv("HULL_SERIAL_LEVELS", "12")
     monkeypatch.setenv("HULL_WALK_SEGMENT", "32")
     s = hull.schedule_defaults()

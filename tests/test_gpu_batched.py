@@ -46,11 +46,12 @@ def ws(H):
 # (serial_levels, walk_segment, fused_levels); -1 / 0 = library default
 SCHEDULES = {
     "default": (-1, 0, -1),
-    "serial": (99, 0, 0),
-    "parallel": (0, 16, 0),
-    "parallel_seg4": (0, 4, 0),
-    "split3": (3, 32, 0),
-    "wave6": (14, 8, 0, 6),
+    "serial": (99, 0, 0, -1),
+    "parallel": (0, 16, 0, -1),
+    "parallel_seg4": (0, 4, 0, -1),
+    "split3": (3, 32, 0, -1),
+    "wave6": (14, 8, 0, 6, 16),
+    "wave6_8": (14, 8, 0, 6, 8),
 }
 
 
@@ -205,13 +206,14 @@ def test_autotuner_schedules_agree(H, ws):
     pts, off, _ = workloads.cfg4(H=120, lo=3.0, hi=13.0)
     x = torch.from_numpy(pts).cuda()
     best, times = autotune.tune(x, off, reps=1, serial_levels=(6, 9, 99), walk_segments=(8, 32),
-                                save=False, log=say)
-    assert (best.serial_levels, best.walk_segment) in times
+                                wave_levels=(-1, 7), save=False, log=say)
+    assert (best.serial_levels, best.walk_segment, best.wave_from) in times
     ref = None
-    for sl, seg in times:
-        f, fo = H.hull_batched_sync(x, off, schedule=H.Schedule(sl, seg, 0), ws=ws)
+    for sl, seg, wf in times:
+        f, fo = H.hull_batched_sync(x, off, schedule=H.Schedule(sl, seg, 0, wf, 16), ws=ws)
         cur = [validate.canonical(f[fo[h]:fo[h + 1]].cpu().numpy()) for h in range(len(off) - 1)]
         if ref is None:
             ref = cur
         else:
-            assert all(a.shape == b.shape and (a == b).all() for a, b in zip(ref, cur)), (sl, seg)
+            assert all(a.shape == b.shape and (a == b).all() for a, b in zip(ref, cur)), \
+                (sl, seg, wf)

@@ -47,10 +47,10 @@ def ws(H):
 # boundary, and with a split after level 3.  The wave strategies run the
 # lane-serial levels from level 5 (or 7) up one merge per wavefront.
 STRATEGIES = {
-    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": ""},
-    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16", "HULL_WAVE_LEVEL": ""},
-    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4", "HULL_WAVE_LEVEL": ""},
-    "split3_seg64": {"HULL_SERIAL_LEVELS": "3", "HULL_WALK_SEGMENT": "64", "HULL_WAVE_LEVEL": ""},
+    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "-1"},
+    "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16", "HULL_WAVE_LEVEL": "-1"},
+    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4", "HULL_WAVE_LEVEL": "-1"},
+    "split3_seg64": {"HULL_SERIAL_LEVELS": "3", "HULL_WALK_SEGMENT": "64", "HULL_WAVE_LEVEL": "-1"},
     "wave5": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
               "HULL_WAVE_LANES": "16"},
     "wave5_8": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",

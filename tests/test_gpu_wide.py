@@ -20,8 +20,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 XY, Z = 1 << 30, 1 << 42
 
 STRATEGIES = {
-    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": ""},
-    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4", "HULL_WAVE_LEVEL": ""},
+    "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "-1"},
+    "parallel_seg4": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "4", "HULL_WAVE_LEVEL": "-1"},
     "wave5": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5"},
     "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": ""},
 }
