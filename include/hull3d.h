@@ -129,6 +129,18 @@ int32_t hull_full_f32(const float* d_xyz, int64_t n, int32_t bits, int32_t* d_fa
 int32_t hull_lower_f32(const float* d_xyz, int64_t n, int32_t bits, int32_t* d_faces, int64_t cap,
                        int64_t* d_info, void* d_ws, size_t ws_bytes, void* stream);
 
+/* hull_full for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same call
+ * without a workspace argument.  Its scratch memory is a fixed 64 MiB device
+ * array of the library (one per GPU, held until the process ends), so n is
+ * limited to the sizes whose hull_workspace_bytes(n, HULL_WS_STANDARD) fits
+ * in 64 MiB; larger n returns HULL_EWORKSPACE before launching anything.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race and must not be
+ * made.  Uses the current device (the stream must belong to it). */
+int32_t hull_full_noalloc(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int64_t cap,
+                          int64_t* d_info, void* stream);
+
 /* Merge schedule of a batched call (every field < 0, or 0 for walk_segment,
  * takes the library default):
  *   serial_levels  merge levels 1..serial_levels run one lane per merge (the

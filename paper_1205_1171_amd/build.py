@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libhull3d.so")
-SOURCES = ["plan.cpp", "sort.hip", "merge.hip", "merge_par.hip", "volume.hip", "adjacency.hip", "delaunay.hip", "wide.hip"]
+SOURCES = ["plan.cpp", "sort.hip", "merge.hip", "merge_par.hip", "volume.hip", "adjacency.hip", "delaunay.hip", "wide.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",
