@@ -6,10 +6,12 @@ level of the lower and upper runs, face extraction) on the n = 2^24 workload
 value = Mpoints/s = n / (time per step).
 
 Also reported on the same line:
-  roofline        the lane-serial merge kernel of levels 5-9 (k_merge_level,
-                  the largest share of the step): algorithmic bytes per launch (from the
-                  oracle's per-level counters: 4 B per event read, 4 B per
-                  event written, 28 B per point touched) over its average
+  roofline        the merge kernel with the largest share of the step (the
+                  lane-serial k_merge_level, the lane-group k_merge_wave or
+                  the LDS-staged k_merge_level_lds, whichever takes the most
+                  time over its levels): algorithmic bytes per launch (from
+                  the oracle's per-level counters: 4 B per event read, 4 B
+                  per event written, 28 B per point touched) over its average
                   launch time, measured with HIP events recorded around each
                   of its launches on the library's stream in the timed steps;
   levels          the same figure for every merge level (the parallel levels
