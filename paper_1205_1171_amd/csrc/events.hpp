@@ -26,6 +26,72 @@ struct RunPtrs {
   int zs;
 };
 
+// Working links (pv, nx) of a merge's points, in one of three places.  The
+// merge kernels read and write them only through get / set_pv / set_nx /
+// set, so one merge loop serves all three.
+//
+// In global memory: one int2 per point, indexed like the point array.
+struct GlobalLinks {
+  int2* p;
+  __device__ __forceinline__ int2 get(int i) const { return p[i]; }
+  __device__ __forceinline__ void set_pv(int i, int v) const { p[i].x = v; }
+  __device__ __forceinline__ void set_nx(int i, int v) const { p[i].y = v; }
+  __device__ __forceinline__ void set(int i, int pv, int nx) const { p[i] = make_int2(pv, nx); }
+};
+
+// In LDS, as block-local ranks (kNil stays -1) in a narrow signed type: one
+// lane's merge of up to kLinkLdsLane points in int8, a lane group's merge in
+// int16 while the block's groups need at most kLinkLdsGroupBytes.  Entry i
+// sits at p[i * STRIDE] (STRIDE 64: the entries of a wave's 64 lanes
+// interleaved, so that a wave-wide access spans consecutive banks).  Indices
+// and link values are block-local.
+constexpr int kLinkLdsLane = 128;
+constexpr int kLinkLdsGroupBytes = 32768;
+template <class T>
+struct __align__(2 * sizeof(T)) LinkPair {
+  T pv, nx;
+};
+template <class T, int STRIDE>
+struct LdsLinks {
+  LinkPair<T>* p;
+  __device__ __forceinline__ int2 get(int i) const {
+    const LinkPair<T> e = p[i * STRIDE];
+    return make_int2(e.pv, e.nx);
+  }
+  __device__ __forceinline__ void set_pv(int i, int v) const { p[i * STRIDE].pv = (T)v; }
+  __device__ __forceinline__ void set_nx(int i, int v) const { p[i * STRIDE].nx = (T)v; }
+  __device__ __forceinline__ void set(int i, int pv, int nx) const {
+    LinkPair<T> e;
+    e.pv = (T)pv;
+    e.nx = (T)nx;
+    p[i * STRIDE] = e;
+  }
+};
+
+// In LDS as above, for a merge loop that works in global ranks: indices and
+// link values are shifted by the block start on the way in and out.
+template <class T>
+struct LdsLinksShifted {
+  LinkPair<T>* p;
+  int base;
+  __device__ __forceinline__ int2 get(int i) const {
+    const LinkPair<T> e = p[i - base];
+    return make_int2(e.pv < 0 ? kNil : e.pv + base, e.nx < 0 ? kNil : e.nx + base);
+  }
+  __device__ __forceinline__ void set_pv(int i, int v) const {
+    p[i - base].pv = (T)(v == kNil ? -1 : v - base);
+  }
+  __device__ __forceinline__ void set_nx(int i, int v) const {
+    p[i - base].nx = (T)(v == kNil ? -1 : v - base);
+  }
+  __device__ __forceinline__ void set(int i, int pv, int nx) const {
+    LinkPair<T> e;
+    e.pv = (T)(pv == kNil ? -1 : pv - base);
+    e.nx = (T)(nx == kNil ? -1 : nx - base);
+    p[i - base] = e;
+  }
+};
+
 // The hulls of a call (rank offsets) and the level schedule built for every
 // level on the device: the merges (pairs of adjacent blocks inside a hull)
 // and the unpaired trailing blocks that are copied across.

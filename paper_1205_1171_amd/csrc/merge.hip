@@ -39,8 +39,8 @@ namespace hull {
 // (Lev, Rev), the merged movie (out) and the -inf link arrays (pv0, nx0) are
 // global and in global ranks.  Returns the merged movie's length, -1 after an
 // internal error.
-template <class PT>
-__device__ __forceinline__ int merge_core(const PT* pts, int2* lk, int* pv0, int* nx0, int base,
+template <class PT, class LK>
+__device__ __forceinline__ int merge_core(const PT* pts, LK lk, int* pv0, int* nx0, int base,
                           const Event* Lev, int nL, const Event* Rev, int nR, Event* out,
                           Header* h, int64_t s, int64_t m, int64_t e, int zs) {
   const int64_t cap = 2 * (e - s);
@@ -94,7 +94,7 @@ __device__ __forceinline__ int merge_core(const PT* pts, int2* lk, int* pv0, int
   T.kind = 0;
   int nu, pu, pvv, nv;
   {
-    const int2 lu = lk[u], lv = lk[v];
+    const int2 lu = lk.get(u), lv = lk.get(v);
     pu = lu.x;
     nu = lu.y;
     pvv = lv.x;
@@ -231,9 +231,9 @@ __device__ __forceinline__ int merge_core(const PT* pts, int2* lk, int* pv0, int
       emit = bi == 0 ? (bw < u) : (bw > v);
       // the event sets nx(a) and pv(b) (and, inserting w, both links of w)
       const int na = bk ? bw : bb, pb = bk ? bw : ba;
-      lk[ba].y = na;  // nx(a)
-      lk[bb].x = pb;  // pv(b)
-      if (bk) lk[bw] = make_int2(ba, bb);  // the inserted point's links
+      lk.set_nx(ba, na);
+      lk.set_pv(bb, pb);
+      if (bk) lk.set(bw, ba, bb);  // the inserted point's links
       // links of u and v it changed (w is never u or v when inserted)
       unsigned d = 0;
       if (ba == u) { nu = na; d |= 1u; }
@@ -246,13 +246,13 @@ __device__ __forceinline__ int merge_core(const PT* pts, int2* lk, int* pv0, int
       if (bi == 2 || bi == 3) {
         u = bi == 2 ? nu : pu;
         Pu = pts[u];
-        const int2 l = lk[u];
+        const int2 l = lk.get(u);
         pu = l.x;
         nu = l.y;
       } else {
         v = bi == 4 ? pvv : nv;
         Pv = pts[v];
-        const int2 l = lk[v];
+        const int2 l = lk.get(v);
         pvv = l.x;
         nv = l.y;
       }
@@ -281,7 +281,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     R.len_out[s] = 0;
     return;
   }
-  const int k = merge_core((const PT*)R.pts, R.lk, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+  const int k = merge_core((const PT*)R.pts, GlobalLinks{R.lk}, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
                            R.ev_out + 2 * s, h, s, m, e, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
 }
@@ -427,8 +427,46 @@ __global__ void __launch_bounds__(64) k_merge_level_lds(LevelArgs A) {
     const int pv = R.pv0[s + j], nx = R.nx0[s + j];
     K[j] = make_int2(pv == kNil ? kNil : pv - b, nx == kNil ? kNil : nx - b);
   }
-  const int k = merge_core(P, K, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+  const int k = merge_core(P, GlobalLinks{K}, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
                            R.ev_out + 2 * s, A.h, 0, m - s, e - s, R.zs);
+  R.len_out[s] = k < 0 ? 0 : k;
+}
+
+// Lane-serial levels with each lane's working links in LDS as block-local
+// int8 ranks (blocks of up to kLinkLdsLane points, the lanes of a wave
+// interleaved): the merge's scattered link reads and writes stay on chip, and
+// the level needs no copy of the -inf links into a global working array.
+// Points, child events and the merged movie stay in global memory.  Dynamic
+// LDS: width x 64 link pairs of 2 bytes.
+template <class PT>
+__global__ void __launch_bounds__(64) k_merge_level_lk(LevelArgs A) {
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const RunPtrs& R = A.run[blockIdx.y];
+  if (!R.pts || t >= A.S.moff[A.S.H]) return;
+  const int* perm = A.perm[blockIdx.y];
+  const int64_t g = perm ? perm[t] : t;
+  const int2 se = A.S.mlist[g];
+  const int64_t s = se.x, m = s + A.half, e = se.y;
+  if (A.h->err) {
+    R.len_out[s] = 0;
+    return;
+  }
+  const int nL = R.len_in[s], nR = R.len_in[m];
+  if (nL < 0 || nR < 0 || nL > 2 * (m - s) || nR > 2 * (e - m) || e - s > A.width ||
+      A.width > kLinkLdsLane) {
+    atomicCAS(&A.h->err, 0, HULL_EINTERNAL);
+    R.len_out[s] = 0;
+    return;
+  }
+  const LdsLinks<signed char, 64> K{(LinkPair<signed char>*)dyn_lds + threadIdx.x};
+  const int w = (int)(e - s), b = (int)s;
+  for (int j = 0; j < w; ++j) {
+    const int pv = R.pv0[s + j], nx = R.nx0[s + j];
+    K.set(j, pv == kNil ? -1 : pv - b, nx == kNil ? -1 : nx - b);
+  }
+  const int k = merge_core((const PT*)R.pts + s, K, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL,
+                           R.ev_in + 2 * m, nR, R.ev_out + 2 * s, A.h, 0, m - s, e - s, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
 }
 
@@ -674,6 +712,7 @@ struct Opts {
   int serial_max, seg;
   int wave_from;   // first lane-serial level run by lane groups (0: none)
   int wave_lanes;  // lanes per merge at level wave_from (8, 16, 32 or 64), doubling per level
+  bool lds_links;  // working links in LDS where they fit (HULL_LDS_LINKS=0: global)
 };
 
 static Opts resolve(const hull_schedule_t* sc) {
@@ -685,6 +724,7 @@ static Opts resolve(const hull_schedule_t* sc) {
   o.wave_from = wf > 0 ? std::max(wf, kLdsLevels + 1) : 0;
   const int wl = sc && sc->wave_lanes > 0 ? sc->wave_lanes : env_int("HULL_WAVE_LANES", 8);
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
+  o.lds_links = env_int("HULL_LDS_LINKS", 1) != 0;
   return o;
 }
 
@@ -773,6 +813,14 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     A.width = int64_t(1) << k;
     A.half = A.width >> 1;
     const bool serial = k <= opt.serial_max;
+    // lane groups at this level, and where the working links live
+    const bool wave = serial && k > kLdsLevels && opt.wave_from > 0 && k >= opt.wave_from;
+    const int lanes = wave ? std::min(64, opt.wave_lanes << std::min(k - opt.wave_from, 3)) : 0;
+    const bool lds_lane = serial && k > kLdsLevels && !wave && opt.lds_links &&
+                          A.width <= kLinkLdsLane;
+    const bool lds_group = wave && opt.lds_links &&
+                           (256 / lanes) * A.width * (int64_t)sizeof(LinkPair<short>) <=
+                               kLinkLdsGroupBytes;
     // the schedule of this level
     int32_t rc = HULL_OK;
     const bool single = S.H == 1;
@@ -798,7 +846,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       Q.len_in = R.len_in;
       Q.ev_out = R.ev_out;
       Q.len_out = R.len_out;
-      if (R.pts && serial && k > kLdsLevels)
+      if (R.pts && serial && k > kLdsLevels && !lds_lane && !lds_group)
         hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.lk, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
@@ -823,16 +871,24 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
         hipLaunchKernelGGL(k_work_scan, dim3(1, 2), dim3(64), 0, s, B);
         hipLaunchKernelGGL(k_work_place, grid, dim3(256), 0, s, B);
       }
-      if (opt.wave_from > 0 && k >= opt.wave_from) {
+      if (wave) {
         // lanes per merge double with every level (merges halve), so that
         // every lane-group level keeps about the same number of waves
-        const int lanes = std::min(64, opt.wave_lanes << std::min(k - opt.wave_from, 3));
         const int per = 256 / lanes;  // merges per block
         const dim3 wg((unsigned)((bound + per - 1) / per), 2);
-        if (lanes == 64) hipLaunchKernelGGL((k_merge_wave<PT, 64>), wg, dim3(256), 0, s, B);
-        else if (lanes == 32) hipLaunchKernelGGL((k_merge_wave<PT, 32>), wg, dim3(256), 0, s, B);
-        else if (lanes == 16) hipLaunchKernelGGL((k_merge_wave<PT, 16>), wg, dim3(256), 0, s, B);
-        else hipLaunchKernelGGL((k_merge_wave<PT, 8>), wg, dim3(256), 0, s, B);
+        const size_t lds = lds_group ? (size_t)per * A.width * sizeof(LinkPair<short>) : 0;
+#define HULL_WAVE(G)                                                                    \
+  if (lds_group) hipLaunchKernelGGL((k_merge_wave<PT, G, true>), wg, dim3(256), lds, s, B); \
+  else hipLaunchKernelGGL((k_merge_wave<PT, G, false>), wg, dim3(256), 0, s, B);
+        if (lanes == 64) { HULL_WAVE(64) }
+        else if (lanes == 32) { HULL_WAVE(32) }
+        else if (lanes == 16) { HULL_WAVE(16) }
+        else { HULL_WAVE(8) }
+#undef HULL_WAVE
+      } else if (lds_lane) {
+        const dim3 g64((unsigned)((bound + 63) / 64), 2);
+        const size_t lds = (size_t)A.width * 64 * sizeof(LinkPair<signed char>);
+        hipLaunchKernelGGL(k_merge_level_lk<PT>, g64, dim3(64), lds, s, B);
       } else
         hipLaunchKernelGGL(k_merge_level<PT>, grid, dim3(256), 0, s, B);
     } else {

@@ -21,11 +21,18 @@
 #include "common.hpp"
 #include "events.hpp"
 
+#include <type_traits>
+
 namespace hull {
 
-template <class PT, int G>
+// With LDSL the merge's working links sit in LDS as block-local int16 ranks
+// (dynamic LDS: 256 / G merges per block x width link pairs of 4 bytes),
+// loaded by the group from the -inf links; without, in the level's global
+// working array.
+template <class PT, int G, bool LDSL>
 __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "lanes per merge");
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
   // per group of the block: G events of each child movie
   __shared__ Event chunk[256 / G][2][G];
   const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
@@ -52,7 +59,23 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
   }
   const PT* pts = (const PT*)R.pts;
   const int zs = R.zs;
-  int2* lk = R.lk;
+  using LK = typename std::conditional<LDSL, LdsLinksShifted<short>, GlobalLinks>::type;
+  LK lk;
+  if constexpr (LDSL) {
+    if (e - s > A.width || A.width > 32767) {
+      if (lane == 0) {
+        atomicCAS(&h->err, 0, HULL_EINTERNAL);
+        R.len_out[s] = 0;
+      }
+      return;
+    }
+    lk.p = (LinkPair<short>*)dyn_lds + (int64_t)grp * A.width;
+    lk.base = (int)s;
+    for (int j = lane; j < (int)(e - s); j += G) lk.set((int)s + j, R.pv0[s + j], R.nx0[s + j]);
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    lk.p = R.lk;
+  }
   const Event* Lev = R.ev_in + 2 * s;
   const Event* Rev = R.ev_in + 2 * m;
   Event* out = R.ev_out + 2 * s;
@@ -100,7 +123,7 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
   // candidate, whether it exists and is after T.
   int pu, nu, pvv, nv;
   {
-    const int2 lu = lk[u], lv = lk[v];
+    const int2 lu = lk.get(u), lv = lk.get(v);
     pu = lu.x;
     nu = lu.y;
     pvv = lv.x;
@@ -198,9 +221,9 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
       // every lane stores the same values, so that each lane's later loads
       // follow its own stores
       const int na = bk ? bw : bb, pb = bk ? bw : ba;
-      lk[ba].y = na;
-      lk[bb].x = pb;
-      if (bk) lk[bw] = make_int2(ba, bb);
+      lk.set_nx(ba, na);
+      lk.set_pv(bb, pb);
+      if (bk) lk.set(bw, ba, bb);
       if (ba == u) { nu = na; dirty |= 1u; }
       if (bb == u) { pu = pb; dirty |= 2u; }
       if (bb == v) { pvv = pb; dirty |= 4u; }
@@ -209,12 +232,12 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
       emit = true;
       if (win == 2 || win == 3) {
         u = win == 2 ? nu : pu;
-        const int2 l = lk[u];
+        const int2 l = lk.get(u);
         pu = l.x;
         nu = l.y;
       } else {
         v = win == 4 ? pvv : nv;
-        const int2 l = lk[v];
+        const int2 l = lk.get(v);
         pvv = l.x;
         nv = l.y;
       }

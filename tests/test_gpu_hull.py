@@ -45,7 +45,9 @@ def ws(H):
 # movies and faces.  The parallel strategy is also run with walk segments of
 # 4 child events (the minimum), so that most walks start from a tangent found at a segment
 # boundary, and with a split after level 3.  The wave strategies run the
-# lane-serial levels from level 5 (or 7) up one merge per wavefront.
+# lane-serial levels from level 5 (or 7) up on groups of lanes.  By default the
+# working links of lane-serial levels 5-7 and of the lane groups sit in LDS;
+# the *_global_links strategies keep them in global memory.
 STRATEGIES = {
     "serial": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "-1"},
     "parallel": {"HULL_SERIAL_LEVELS": "0", "HULL_WALK_SEGMENT": "16", "HULL_WAVE_LEVEL": "-1"},
@@ -60,6 +62,11 @@ STRATEGIES = {
     "wave7_split10": {"HULL_SERIAL_LEVELS": "10", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "7",
                       "HULL_WAVE_LANES": "32"},
     "default": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": ""},
+    # working links in the level's global array instead of LDS
+    "default_global_links": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "",
+                             "HULL_WAVE_LEVEL": "", "HULL_LDS_LINKS": "0"},
+    "serial_global_links": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "",
+                            "HULL_WAVE_LEVEL": "-1", "HULL_LDS_LINKS": "0"},
 }
 
 
@@ -205,7 +212,8 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
+              "HULL_LDS_LINKS"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
