@@ -247,14 +247,18 @@ def single(args, hull, workloads):
     roofline = levels = None
     S = min(sched.serial_levels, L)
     KL = min(sched.fused_levels, S)  # lowest levels: the LDS-staged kernel
-    W = sched.wave_from if sched.wave_from > 0 else L + 1  # first one-merge-per-wave level
+    W = sched.wave_from if sched.wave_from > 0 else L + 1  # first lane-group level
+    lds_links = os.environ.get("HULL_LDS_LINKS", "1") != "0"
 
     def kernel_of(k):  # k: 1-based level
         if k > S:
             return "parallel strategy (k_par_* kernels, device scans)"
         if k <= KL:
             return "k_merge_level_lds"
-        return "k_merge_wave" if k >= W else "k_merge_level"
+        if k >= W:
+            return "k_merge_wave"
+        # lane-serial blocks of up to 128 points keep their links in LDS
+        return "k_merge_level_lk" if lds_links and k <= 7 else "k_merge_level"
 
     if golden is not None:
         stats = np.array(golden["level_stats_lower"]) + np.array(golden["level_stats_upper"])

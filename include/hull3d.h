@@ -145,14 +145,14 @@ int32_t hull_full_noalloc(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int
  * takes the library default):
  *   serial_levels  merge levels 1..serial_levels run one lane per merge (the
  *                  paper's kernel, Sec. 3); the levels above split each merge
- *                  into time segments walked in parallel (default 9)
+ *                  into time segments walked in parallel (default 10)
  *   walk_segment   child events per walk segment, >= 4 (default 4)
  *   fused_levels   ignored on input (pass 0 or -1); hull_schedule_defaults
  *                  writes the number of LDS-staged lowest levels here
  *   wave_from      lane-serial levels from this one on run one merge per
  *                  group of wave_lanes lanes instead of one per lane (the
  *                  six candidates of an iteration on six lanes, child movies
- *                  through LDS); 0: the default, negative: no level
+ *                  through LDS); 0: the default (8), negative: no level
  *   wave_lanes     lanes per merge at level wave_from: 8, 16, 32 or 64,
  *                  doubling with every level above (merges halve), up to 64
  *                  (0: the default, 8)
@@ -169,10 +169,13 @@ typedef struct hull_schedule_t {
 /* The schedule the library uses when a call passes none (or leaves a field
  * at its default): the built-in defaults, overridden by the environment
  * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT, HULL_WAVE_LEVEL and
- * HULL_WAVE_LANES when set.  On output,
- * fused_levels is the number of lowest lane-serial levels that stage each
- * merge's points and links in LDS (a separate kernel from the other
- * lane-serial levels).  Host, synchronous. */
+ * HULL_WAVE_LANES when set.  On output, fused_levels is the number of lowest
+ * lane-serial levels that stage each merge's points and links in LDS (a
+ * separate kernel from the other lane-serial levels; default 3, at most 4,
+ * environment HULL_LDS_LEVELS).  Above them, lane-serial merges of blocks up
+ * to 128 points and lane-group merges keep only their working links in LDS
+ * (HULL_LDS_LINKS=0: in global memory).  None of this changes a result.
+ * Host, synchronous. */
 int32_t hull_schedule_defaults(hull_schedule_t* out);
 
 /* Bytes of device workspace for hull_full_batched over H hulls of

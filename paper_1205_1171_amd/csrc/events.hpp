@@ -156,11 +156,11 @@ __device__ __forceinline__ Lead lead_of(int4 P, int4 Q, int4 R, int zs) {
 // points with equal x (all triples on such a pair share a standard part),
 // with no 256-bit arithmetic; only when all three vanish (or D0 = D1 = 0)
 // does the full cascade run.
-__device__ __forceinline__ int tri_cmp_mid_body(const int4* pts, Tri A, Tri B, int zs) {
-  Lead a = lead_of(pts[A.a], pts[A.w], pts[A.b], zs);
-  Lead b = lead_of(pts[B.a], pts[B.w], pts[B.b], zs);
-  int sa = a.d0 ? (a.d0 > 0 ? 1 : -1) : (a.d1 > 0) - (a.d1 < 0);
-  int sb = b.d0 ? (b.d0 > 0 ? 1 : -1) : (b.d1 > 0) - (b.d1 < 0);
+// Sign of tau_A - tau_B from coefficients 1-3 of both leading terms; 0 when
+// they do not decide (all three vanish, or D0 = D1 = 0 on a side).
+__device__ __forceinline__ int lead_cmp(const Lead& a, const Lead& b) {
+  const int sa = a.d0 ? (a.d0 > 0 ? 1 : -1) : (a.d1 > 0) - (a.d1 < 0);
+  const int sb = b.d0 ? (b.d0 > 0 ? 1 : -1) : (b.d1 > 0) - (b.d1 < 0);
   if (sa && sb) {
     i128 p = (i128)a.n0 * b.d0 - (i128)b.n0 * a.d0;
     if (!p) {
@@ -169,7 +169,13 @@ __device__ __forceinline__ int tri_cmp_mid_body(const int4* pts, Tri A, Tri B, i
     }
     if (p) return (p > 0 ? 1 : -1) * sa * sb;
   }
-  return tri_cmp_exact(pts, A, B, zs);
+  return 0;
+}
+
+__device__ __forceinline__ int tri_cmp_mid_body(const int4* pts, Tri A, Tri B, int zs) {
+  const int s = lead_cmp(lead_of(pts[A.a], pts[A.w], pts[A.b], zs),
+                         lead_of(pts[B.a], pts[B.w], pts[B.b], zs));
+  return s ? s : tri_cmp_exact(pts, A, B, zs);
 }
 
 // The same on the wide range, where D0, N0, D1, N1 need int128 and their
@@ -201,9 +207,7 @@ __device__ __forceinline__ int bits128(i128 v) {
   return hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
 }
 
-__device__ __forceinline__ int tri_cmp_mid_body(const WPt* pts, Tri A, Tri B, int zs) {
-  const WLead a = lead_of(pts[A.a], pts[A.w], pts[A.b], zs);
-  const WLead b = lead_of(pts[B.a], pts[B.w], pts[B.b], zs);
+__device__ __forceinline__ int lead_cmp(const WLead& a, const WLead& b) {
   const int sa = a.d0 ? (a.d0 > 0 ? 1 : -1) : (a.d1 > 0) - (a.d1 < 0);
   const int sb = b.d0 ? (b.d0 > 0 ? 1 : -1) : (b.d1 > 0) - (b.d1 < 0);
   const int mn = max(max(bits128(a.n0), bits128(a.n1)), max(bits128(b.n0), bits128(b.n1)));
@@ -216,7 +220,13 @@ __device__ __forceinline__ int tri_cmp_mid_body(const WPt* pts, Tri A, Tri B, in
     }
     if (p) return (p > 0 ? 1 : -1) * sa * sb;
   }
-  return tri_cmp_exact(pts, A, B, zs);
+  return 0;
+}
+
+__device__ __forceinline__ int tri_cmp_mid_body(const WPt* pts, Tri A, Tri B, int zs) {
+  const int s = lead_cmp(lead_of(pts[A.a], pts[A.w], pts[A.b], zs),
+                         lead_of(pts[B.a], pts[B.w], pts[B.b], zs));
+  return s ? s : tri_cmp_exact(pts, A, B, zs);
 }
 
 // The mid tier as a call (kernels with many live registers) ...
@@ -235,6 +245,20 @@ __device__ __forceinline__ int ev_cmp(const PT* pts, const Cand& A, const Cand& 
   int s = std_cmp(A.st, B.st);
   if (s) return s;
   return kInlineMid ? tri_cmp_mid_body(pts, A.t, B.t, zs) : tri_cmp_mid(pts, A.t, B.t, zs);
+}
+
+// The same order for callers that hold both triples' points (A's as a0, a1,
+// a2 and B's as b0, b1, b2, in rank order): the mid tier then needs no loads
+// and no call; only the full cascade (rare) reloads them.
+template <class PT>
+__device__ __forceinline__ int ev_cmp_pts(const PT* pts, const Cand& A, const PT& a0, const PT& a1,
+                                          const PT& a2, const Cand& B, const PT& b0, const PT& b1,
+                                          const PT& b2, int zs) {
+  if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
+  const int s = std_cmp(A.st, B.st);
+  if (s) return s;
+  const int m = lead_cmp(lead_of(a0, a1, a2, zs), lead_of(b0, b1, b2, zs));
+  return m ? m : tri_cmp_exact(pts, A.t, B.t, zs);
 }
 
 // Perturbed sign of D when D0 = D1 = 0 (cold path).

@@ -38,8 +38,11 @@ namespace hull {
 // global arrays, the block start for a block staged in LDS.  Child events
 // (Lev, Rev), the merged movie (out) and the -inf link arrays (pv0, nx0) are
 // global and in global ranks.  Returns the merged movie's length, -1 after an
-// internal error.
-template <class PT, class LK>
+// internal error.  kInline: which comparisons take the mid tier inline rather
+// than as a call (0 none, 1 the bridge moves against the last event, 2 all):
+// inline costs registers, a call costs the wave a round trip whenever any of
+// its lanes meets a tie of the standard parts.
+template <int kInline, class PT, class LK>
 __device__ __forceinline__ int merge_core(const PT* pts, LK lk, int* pv0, int* nx0, int base,
                           const Event* Lev, int nL, const Event* Rev, int nR, Event* out,
                           Header* h, int64_t s, int64_t m, int64_t e, int zs) {
@@ -133,7 +136,7 @@ __device__ __forceinline__ int merge_core(const PT* pts, LK lk, int* pv0, int* n
     if (OK) {                                                            \
       const Cand c_ = make_cand(pts, A, W, B, PA, PW, PB, KIND, zs);     \
       ST = c_.st;                                                        \
-      OK = !haveT || ev_cmp(pts, c_, T, zs) > 0;                         \
+      OK = !haveT || ev_cmp<(kInline >= 1)>(pts, c_, T, zs) > 0;         \
     }                                                                    \
   }
       HULL_SLOT(1u, ok2, st2, nu, u, nu, v, Pu, pts[nu], Pv, 1)
@@ -155,7 +158,7 @@ __device__ __forceinline__ int merge_core(const PT* pts, LK lk, int* pv0, int* n
       y_.t = Tri{ba, bw, bb};                                            \
       y_.st = bbs;                                                       \
       y_.kind = bk;                                                      \
-      take_ = ev_cmp(pts, x_, y_, zs) < 0;                               \
+      take_ = ev_cmp<(kInline >= 2)>(pts, x_, y_, zs) < 0;                   \
     }                                                                    \
     if (take_) {                                                         \
       bbi = (IDX);                                                       \
@@ -194,7 +197,7 @@ __device__ __forceinline__ int merge_core(const PT* pts, LK lk, int* pv0, int* n
       y_.t = Tri{ba, bw, bb};                                            \
       y_.st = bs;                                                        \
       y_.kind = 0;                                                       \
-      take_ = ev_cmp(pts, x_, y_, zs) < 0;                         \
+      take_ = ev_cmp<(kInline >= 2)>(pts, x_, y_, zs) < 0;                   \
     }                                                                    \
     if (take_) {                                                         \
       bi = (IDX);                                                        \
@@ -281,7 +284,7 @@ __device__ void merge_one(const RunPtrs& R, Header* h, int64_t s, int64_t m, int
     R.len_out[s] = 0;
     return;
   }
-  const int k = merge_core((const PT*)R.pts, GlobalLinks{R.lk}, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+  const int k = merge_core<1>((const PT*)R.pts, GlobalLinks{R.lk}, R.pv0, R.nx0, 0, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
                            R.ev_out + 2 * s, h, s, m, e, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
 }
@@ -427,7 +430,7 @@ __global__ void __launch_bounds__(64) k_merge_level_lds(LevelArgs A) {
     const int pv = R.pv0[s + j], nx = R.nx0[s + j];
     K[j] = make_int2(pv == kNil ? kNil : pv - b, nx == kNil ? kNil : nx - b);
   }
-  const int k = merge_core(P, GlobalLinks{K}, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
+  const int k = merge_core<2>(P, GlobalLinks{K}, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL, R.ev_in + 2 * m, nR,
                            R.ev_out + 2 * s, A.h, 0, m - s, e - s, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
 }
@@ -465,7 +468,7 @@ __global__ void __launch_bounds__(64) k_merge_level_lk(LevelArgs A) {
     const int pv = R.pv0[s + j], nx = R.nx0[s + j];
     K.set(j, pv == kNil ? -1 : pv - b, nx == kNil ? -1 : nx - b);
   }
-  const int k = merge_core((const PT*)R.pts + s, K, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL,
+  const int k = merge_core<1>((const PT*)R.pts + s, K, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL,
                            R.ev_in + 2 * m, nR, R.ev_out + 2 * s, A.h, 0, m - s, e - s, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
 }
@@ -713,6 +716,8 @@ struct Opts {
   int wave_from;   // first lane-serial level run by lane groups (0: none)
   int wave_lanes;  // lanes per merge at level wave_from (8, 16, 32 or 64), doubling per level
   bool lds_links;  // working links in LDS where they fit (HULL_LDS_LINKS=0: global)
+  int lds_levels;  // lowest levels with points and links staged in LDS (at most kLdsLevels;
+                   // above them, the links alone)
 };
 
 static Opts resolve(const hull_schedule_t* sc) {
@@ -725,6 +730,7 @@ static Opts resolve(const hull_schedule_t* sc) {
   const int wl = sc && sc->wave_lanes > 0 ? sc->wave_lanes : env_int("HULL_WAVE_LANES", 8);
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
   o.lds_links = env_int("HULL_LDS_LINKS", 1) != 0;
+  o.lds_levels = std::min(std::max(env_int("HULL_LDS_LEVELS", 3), 0), kLdsLevels);
   return o;
 }
 
@@ -814,9 +820,9 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     A.half = A.width >> 1;
     const bool serial = k <= opt.serial_max;
     // lane groups at this level, and where the working links live
-    const bool wave = serial && k > kLdsLevels && opt.wave_from > 0 && k >= opt.wave_from;
+    const bool wave = serial && k > opt.lds_levels && opt.wave_from > 0 && k >= opt.wave_from;
     const int lanes = wave ? std::min(64, opt.wave_lanes << std::min(k - opt.wave_from, 3)) : 0;
-    const bool lds_lane = serial && k > kLdsLevels && !wave && opt.lds_links &&
+    const bool lds_lane = serial && k > opt.lds_levels && !wave && opt.lds_links &&
                           A.width <= kLinkLdsLane;
     const bool lds_group = wave && opt.lds_links &&
                            (256 / lanes) * A.width * (int64_t)sizeof(LinkPair<short>) <=
@@ -846,11 +852,11 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       Q.len_in = R.len_in;
       Q.ev_out = R.ev_out;
       Q.len_out = R.len_out;
-      if (R.pts && serial && k > kLdsLevels && !lds_lane && !lds_group)
+      if (R.pts && serial && k > opt.lds_levels && !lds_lane && !lds_group)
         hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.lk, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
-    if (serial && k <= kLdsLevels) {
+    if (serial && k <= opt.lds_levels) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 63) / 64), 2);
       if (k == 1) hipLaunchKernelGGL((k_merge_level_lds<PT, 2>), grid, dim3(64), 0, s, A);
@@ -1095,7 +1101,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
   const hull::Opts o = hull::resolve(nullptr);
   out->serial_levels = o.serial_max;
   out->walk_segment = o.seg;
-  out->fused_levels = hull::kLdsLevels;
+  out->fused_levels = o.lds_levels;
   out->wave_from = o.wave_from;
   out->wave_lanes = o.wave_lanes;
   out->reserved = 0;

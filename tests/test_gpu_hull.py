@@ -67,6 +67,11 @@ STRATEGIES = {
                              "HULL_WAVE_LEVEL": "", "HULL_LDS_LINKS": "0"},
     "serial_global_links": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "",
                             "HULL_WAVE_LEVEL": "-1", "HULL_LDS_LINKS": "0"},
+    # points and links staged in LDS up to level 4 (16-point blocks), and not at all
+    "lds4": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "",
+             "HULL_LDS_LEVELS": "4"},
+    "lds0": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "",
+             "HULL_LDS_LEVELS": "0"},
 }
 
 
@@ -213,7 +218,7 @@ def _golden(name):
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
     for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
-              "HULL_LDS_LINKS"):
+              "HULL_LDS_LINKS", "HULL_LDS_LEVELS"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
