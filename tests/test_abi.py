@@ -152,13 +152,20 @@ def test_delaunay_argument_errors(L):
 def test_schedule_defaults(L, monkeypatch):
     """Built-in defaults, the environment overrides, and the number of
     LDS-staged levels reported in fused_levels."""
-    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES"):
+    for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
+              "HULL_LDS_LEVELS"):
         monkeypatch.delenv(k, raising=False)
     s = hull.schedule_defaults()
     assert (s.serial_levels, s.walk_segment, s.wave_from, s.wave_lanes) == (10, 4, 8, 8)
     assert 0 <= s.fused_levels <= s.serial_levels
-    monkeypatch.setenv("HULL_WAVE_LEVEL", "2")  # raised above the LDS-staged levels
-    assert hull.schedule_defaults().wave_from == s.fused_levels + 1
+    assert s.fused_levels == 3
+    monkeypatch.setenv("HULL_LDS_LEVELS", "9")  # at most 4 levels stage points in LDS
+    assert hull.schedule_defaults().fused_levels == 4
+    monkeypatch.setenv("HULL_LDS_LEVELS", "0")
+    assert hull.schedule_defaults().fused_levels == 0
+    monkeypatch.delenv("HULL_LDS_LEVELS")
+    monkeypatch.setenv("HULL_WAVE_LEVEL", "2")  # raised above the levels LDS staging can take
+    assert hull.schedule_defaults().wave_from == 5
     monkeypatch.setenv("HULL_WAVE_LEVEL", "-1")
     assert hull.schedule_defaults().wave_from == 0
     monkeypatch.delenv("HULL_WAVE_LEVEL")
