@@ -261,6 +261,18 @@ __device__ __forceinline__ int ev_cmp_pts(const PT* pts, const Cand& A, const PT
   return m ? m : tri_cmp_exact(pts, A.t, B.t, zs);
 }
 
+// The same for a candidate A whose points the caller holds (a0, a1, a2) against
+// an event B: a tie loads only B's points.
+template <class PT>
+__device__ __forceinline__ int ev_cmp_half(const PT* pts, const Cand& A, const PT& a0, const PT& a1,
+                                           const PT& a2, const Cand& B, int zs) {
+  if (A.t.a == B.t.a && A.t.w == B.t.w && A.t.b == B.t.b) return 0;
+  const int s = std_cmp(A.st, B.st);
+  if (s) return s;
+  const int m = lead_cmp(lead_of(a0, a1, a2, zs), lead_of(pts[B.t.a], pts[B.t.w], pts[B.t.b], zs));
+  return m ? m : tri_cmp_exact(pts, A.t, B.t, zs);
+}
+
 // Perturbed sign of D when D0 = D1 = 0 (cold path).
 template <class PT>
 __device__ __noinline__ int d_sign_slow(PT P, PT Q, PT R) {

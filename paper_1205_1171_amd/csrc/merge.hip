@@ -130,14 +130,16 @@ __device__ __forceinline__ int merge_core(const PT* pts, LK lk, int* pv0, int* n
       break;
     }
     if (dirty) {
-#define HULL_SLOT(BIT, OK, ST, LINK, A, W, B, PA, PW, PB, KIND)            \
-  if (dirty & (BIT)) {                                                   \
-    OK = (LINK) != kNil;                                                 \
-    if (OK) {                                                            \
-      const Cand c_ = make_cand(pts, A, W, B, PA, PW, PB, KIND, zs);     \
-      ST = c_.st;                                                        \
-      OK = !haveT || ev_cmp<(kInline >= 1)>(pts, c_, T, zs) > 0;         \
-    }                                                                    \
+#define HULL_SLOT(BIT, OK, ST, LINK, A, W, B, PA, PW, PB, KIND)                  \
+  if (dirty & (BIT)) {                                                         \
+    OK = (LINK) != kNil;                                                       \
+    if (OK) {                                                                  \
+      const PT pa_ = (PA), pw_ = (PW), pb_ = (PB);                             \
+      const Cand c_ = make_cand(pts, A, W, B, pa_, pw_, pb_, KIND, zs);        \
+      ST = c_.st;                                                              \
+      OK = !haveT || (kInline >= 1 ? ev_cmp_half(pts, c_, pa_, pw_, pb_, T, zs) \
+                                   : ev_cmp(pts, c_, T, zs)) > 0;              \
+    }                                                                          \
   }
       HULL_SLOT(1u, ok2, st2, nu, u, nu, v, Pu, pts[nu], Pv, 1)
       HULL_SLOT(2u, ok3, st3, pu, pu, u, v, pts[pu], Pu, Pv, 0)
@@ -464,10 +466,20 @@ __global__ void __launch_bounds__(64) k_merge_level_lk(LevelArgs A) {
   }
   const LdsLinks<signed char, 64> K{(LinkPair<signed char>*)dyn_lds + threadIdx.x};
   const int w = (int)(e - s), b = (int)s;
-  for (int j = 0; j < w; ++j) {
-    const int pv = R.pv0[s + j], nx = R.nx0[s + j];
-    K.set(j, pv == kNil ? -1 : pv - b, nx == kNil ? -1 : nx - b);
+  auto local = [b](int r) { return r == kNil ? -1 : r - b; };
+  int j = 0;
+  if ((s & 3) == 0) {  // 16-byte loads of four links at a time
+    const int4* p4 = (const int4*)(R.pv0 + s);
+    const int4* n4 = (const int4*)(R.nx0 + s);
+    for (; j + 4 <= w; j += 4) {
+      const int4 pv = p4[j >> 2], nx = n4[j >> 2];
+      K.set(j, local(pv.x), local(nx.x));
+      K.set(j + 1, local(pv.y), local(nx.y));
+      K.set(j + 2, local(pv.z), local(nx.z));
+      K.set(j + 3, local(pv.w), local(nx.w));
+    }
   }
+  for (; j < w; ++j) K.set(j, local(R.pv0[s + j]), local(R.nx0[s + j]));
   const int k = merge_core<1>((const PT*)R.pts + s, K, R.pv0, R.nx0, b, R.ev_in + 2 * s, nL,
                            R.ev_in + 2 * m, nR, R.ev_out + 2 * s, A.h, 0, m - s, e - s, R.zs);
   R.len_out[s] = k < 0 ? 0 : k;
