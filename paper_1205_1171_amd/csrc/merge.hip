@@ -485,6 +485,28 @@ __global__ void __launch_bounds__(64) k_merge_level_lk(LevelArgs A) {
   R.len_out[s] = k < 0 ? 0 : k;
 }
 
+// Level 1: the merge of two single points has no events (neither chain has a
+// link to move along), so it is the splice of their -inf chains and an empty
+// movie.  The same result as the merge loop, without its machinery.
+__global__ void __launch_bounds__(256) k_merge_level1(LevelArgs A) {
+  const RunPtrs& R = A.run[blockIdx.y];
+  if (!R.pts) return;
+  const int64_t M = A.S.moff[A.S.H];
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < M;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int2 se = A.S.mlist[g];
+    const int s = se.x;
+    if (A.h->err || se.y - se.x != 2 || R.len_in[s] != 0 || R.len_in[s + 1] != 0) {
+      if (!A.h->err) atomicCAS(&A.h->err, 0, HULL_EINTERNAL);
+      R.len_out[s] = 0;
+      continue;
+    }
+    R.nx0[s] = s + 1;
+    R.pv0[s + 1] = s;
+    R.len_out[s] = 0;
+  }
+}
+
 // The unpaired trailing block of a hull at this level keeps its movie: copy
 // it across (a hull already complete keeps its movie where it is).
 __global__ void __launch_bounds__(256) k_passthrough(LevelArgs A) {
@@ -868,7 +890,10 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
         hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.lk, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
-    if (serial && k <= opt.lds_levels) {
+    if (serial && k == 1) {
+      const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
+      hipLaunchKernelGGL(k_merge_level1, dim3(grid_for(bound), 2), dim3(256), 0, s, A);
+    } else if (serial && k <= opt.lds_levels) {
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 63) / 64), 2);
       if (k == 1) hipLaunchKernelGGL((k_merge_level_lds<PT, 2>), grid, dim3(64), 0, s, A);
