@@ -752,6 +752,8 @@ struct Opts {
   bool lds_links;  // working links in LDS where they fit (HULL_LDS_LINKS=0: global)
   int lds_levels;  // lowest levels with points and links staged in LDS (at most kLdsLevels;
                    // above them, the links alone)
+  int order_from;     // lane-serial levels from this one list their merges in work order
+  int64_t order_min;  // ... when the level bounds at least this many merges
 };
 
 static Opts resolve(const hull_schedule_t* sc) {
@@ -765,6 +767,8 @@ static Opts resolve(const hull_schedule_t* sc) {
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
   o.lds_links = env_int("HULL_LDS_LINKS", 1) != 0;
   o.lds_levels = std::min(std::max(env_int("HULL_LDS_LEVELS", 3), 0), kLdsLevels);
+  o.order_from = env_int("HULL_ORDER_LEVEL", kOrderFromLevel);
+  o.order_min = std::max(env_int("HULL_ORDER_MIN", (int)kOrderMinMerges), 0);
   return o;
 }
 
@@ -904,7 +908,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 255) / 256), 2);
       LevelArgs B = A;
-      if (k >= kOrderFromLevel && bound >= kOrderMinMerges) {
+      if (k >= opt.order_from && bound >= opt.order_min) {
         for (int r = 0; r < 2; ++r) {
           B.perm[r] = (int*)(ws + pl.perm[r]);
           B.wbins[r] = (int*)(ws + pl.wbins[r]);

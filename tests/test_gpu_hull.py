@@ -72,6 +72,10 @@ STRATEGIES = {
              "HULL_LDS_LEVELS": "4"},
     "lds0": {"HULL_SERIAL_LEVELS": "", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "",
              "HULL_LDS_LEVELS": "0"},
+    # the work order (merges listed by child event count) at every level from 4
+    # and for any number of merges, lane-serial and lane groups
+    "ordered": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "7",
+                "HULL_WAVE_LANES": "8", "HULL_ORDER_LEVEL": "4", "HULL_ORDER_MIN": "0"},
 }
 
 
@@ -218,7 +222,7 @@ def _golden(name):
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
     for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
-              "HULL_LDS_LINKS", "HULL_LDS_LEVELS"):
+              "HULL_LDS_LINKS", "HULL_LDS_LEVELS", "HULL_ORDER_LEVEL", "HULL_ORDER_MIN"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
