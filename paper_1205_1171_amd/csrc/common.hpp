@@ -23,8 +23,8 @@ constexpr int kRadixBits = 8;
 constexpr int kBuckets = 1 << kRadixBits;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
-constexpr int kStrideBlocks = 2048;  // grid of the grid-stride kernels
-constexpr int kScanDevGrid = 512;    // tile blocks per job of a device-length scan
+constexpr int kStrideBlocks = 1024;  // grid of the grid-stride kernels
+constexpr int kScanDevGrid = 128;    // tile blocks per job of a device-length scan
 constexpr int kSegKeep = 2;  // bridge events a walk segment keeps from its counting pass
 constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
 constexpr int kWorkBins = 1024;     // child-event counts told apart when ordering merges
