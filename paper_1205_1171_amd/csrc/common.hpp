@@ -98,6 +98,9 @@ struct Plan {
   size_t segTmp[2], segTmpUV[2];  // the first kSegKeep bridge events of each segment
   size_t bev[2], buv[2], nB[2], boff[2], uv0[2], surv[2], jb[2], pre[2];
   size_t aR[2], aL[2], aT[2], wf[2];
+  // status words of the parallel strategy's one-launch scans (kChainJobs x chain_stride)
+  size_t chain_words;
+  int64_t chain_stride;
   // face counts of the hulls of a batch
   size_t fcnt;
   size_t total;
@@ -160,6 +163,7 @@ int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len
 // Several such scans (same add and cap, each its own device length) in one
 // set of launches.  partials must hold kMaxScanJobs * (cap / 4096 + 2) ints.
 constexpr int kMaxScanJobs = 8;
+constexpr int kChainJobs = 16;  // job slots of one parallel level's one-launch scans
 struct ScanJob {
   const int32_t* in;
   int32_t* out;
@@ -172,5 +176,13 @@ struct ScanJobs {
 };
 int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_t* partials,
                                  hipStream_t s);
+// The same scans in one launch (a chained scan).  Job j publishes one status
+// word per tile at words + j * wstride (wstride >= cap / 4096 rounded up);
+// epoch (1 .. 2^30 - 1) tells this scan's words from those of earlier scans
+// that used the same words, which must hold zero or another epoch.
+int32_t exclusive_scan_chained(const ScanJobs& J, int add, int64_t cap, unsigned long long* words,
+                               int64_t wstride, unsigned epoch, Header* h, hipStream_t s);
+// Zero count 64-bit words (a kernel: capturable).
+void zero_words(unsigned long long* w, int64_t count, hipStream_t s);
 
 }  // namespace hull

@@ -393,6 +393,8 @@ struct ParLevel {
   int seg_events;   // child events per walk segment
   int64_t seg_cap;  // bound on the walk segments of a level
   int64_t ecap;     // bound on the child events of a level (2n)
+  unsigned long long* chain_words;  // status words of the level's one-launch scans
+  int64_t chain_stride;             // (kChainJobs slots), zeroed once per call
 };
 
 template <class PT>

@@ -796,6 +796,11 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
   P.seg_events = opt.seg;
   P.seg_cap = pl.seg_cap;
   P.ecap = 2 * n;
+  P.chain_words = (unsigned long long*)(ws + pl.chain_words);
+  P.chain_stride = pl.chain_stride;
+  // the one-launch scans of the parallel levels tell their status words
+  // apart by level within the call: clear the words left by an earlier call
+  if (opt.serial_max < levels) zero_words(P.chain_words, kChainJobs * P.chain_stride, s);
   for (int r = 0; r < 2; ++r) {
     bool on = r == 0 ? lower : upper;
     RunPtrs& R = A.run[r];

@@ -722,31 +722,41 @@ static ScanJobs jobs_of(const ParLevel& P, std::initializer_list<int> fields, in
   return J;
 }
 
+// The level's five scans, one launch each, on job slots of their own; the
+// epoch (level and scan) tells their status words from those of earlier
+// levels of the call.
+static int32_t chained(const ParLevel& P, const ScanJobs& J, int slot, int site, int64_t cap,
+                       hipStream_t s) {
+  return exclusive_scan_chained(J, 1, cap, P.chain_words + slot * P.chain_stride, P.chain_stride,
+                                (unsigned)(P.k * 8 + site), P.h, s);
+}
+
 template <class PT>
 int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
+  (void)partials;
   const dim3 g2(kStrideBlocks, 2), b256(256);
   hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
   // per merge: child events, walk segments (length: merges + 1)
-  int32_t rc = exclusive_scan_dev_multi(jobs_of(P, {0, 1}, kCtrMerges), 1, P.S.mcap + 1, partials, s);
+  int32_t rc = chained(P, jobs_of(P, {0, 1}, kCtrMerges), 0, 1, P.S.mcap + 1, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_enum<PT>, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_count, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_claim, g2, b256, 0, s, P);
   // per child event: list entries and lists it allocates (length: events + 1)
-  rc = exclusive_scan_dev_multi(jobs_of(P, {2, 3, 4}, kCtrEvents), 1, P.ecap + 1, partials, s);
+  rc = chained(P, jobs_of(P, {2, 3, 4}, kCtrEvents), 4, 2, P.ecap + 1, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_place, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_fill, g2, b256, 0, s, P);
   hipLaunchKernelGGL(k_par_sort, g2, b256, 0, s, P);
   const dim3 gw(16384, 2), b64(64);
   hipLaunchKernelGGL(k_par_walk<PT>, gw, b64, 0, s, P, 0);
-  rc = exclusive_scan_dev_multi(jobs_of(P, {5}, kCtrSegments), 1, P.seg_cap + 1, partials, s);
+  rc = chained(P, jobs_of(P, {5}, kCtrSegments), 10, 3, P.seg_cap + 1, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_walk<PT>, gw, b64, 0, s, P, 1);
-  rc = exclusive_scan_dev_multi(jobs_of(P, {6}, kCtrMerges), 1, P.S.mcap + 1, partials, s);
+  rc = chained(P, jobs_of(P, {6}, kCtrMerges), 12, 4, P.S.mcap + 1, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_classify<PT>, g2, b256, 0, s, P);
-  rc = exclusive_scan_dev_multi(jobs_of(P, {7}, kCtrEvents), 1, P.ecap + 1, partials, s);
+  rc = chained(P, jobs_of(P, {7}, kCtrEvents), 14, 5, P.ecap + 1, s);
   if (rc) return rc;
   hipLaunchKernelGGL(k_par_scatter<PT>, g2, b256, 0, s, P);
   HULL_LAUNCH_CHECK();

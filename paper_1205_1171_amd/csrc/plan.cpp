@@ -35,6 +35,8 @@ Plan make_plan(int64_t n, int64_t H, int min_seg, int pt_bytes) {
   };
   p.header = take(sizeof(Header));
   p.partials = take(p.partial_len * 4);
+  p.chain_stride = scan_partials_needed(longest) + 1;
+  p.chain_words = take(kChainJobs * p.chain_stride * sizeof(unsigned long long));
   p.pts = take(nn * (size_t)pt_bytes);
   p.off1 = take(2 * sizeof(int64_t));
   p.mcnt = take((hh + 1) * 4);

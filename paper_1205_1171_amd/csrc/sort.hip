@@ -361,6 +361,121 @@ __global__ void __launch_bounds__(kSortThreads)
   }
 }
 
+// The same scans in one launch.  Tile t of a job (blocks stride over the
+// tiles) publishes its sum, then finds the sum of all tiles before it by
+// looking back over their published words, 64 at a time, until one holds an
+// inclusive prefix (a chained scan with decoupled look-back), publishes its
+// own inclusive prefix and writes its outputs.  A word packs a flag (bit 62:
+// the tile's sum; bit 63: the inclusive prefix through the tile), the scan's
+// epoch (bits 32-61; a word of another epoch counts as not yet published) and
+// the 32-bit value, so one atomic load sees all three.  The grid (at most
+// kScanDevGrid blocks per job) is resident at once and a tile waits only for
+// tiles of lower index, which blocks of lower index or earlier strides hold;
+// the wait is bounded anyway (kChainSpins re-reads, then HULL_EINTERNAL).
+constexpr unsigned long long kChainSum = 1ull << 62, kChainIncl = 1ull << 63;
+constexpr unsigned long long kChainEpoch = 0x3fffffffull << 32;
+constexpr int kChainSpins = 1 << 22;
+
+__device__ __forceinline__ unsigned long long chain_load(const unsigned long long* w) {
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void chain_store(unsigned long long* w, unsigned long long v) {
+  __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+    k_scan_chained(ScanJobs J, int add, int64_t cap, unsigned long long* words, int64_t wstride,
+                   unsigned epoch, Header* h) {
+  const ScanJob& jb = J.j[blockIdx.y];
+  const int64_t len = dev_len(jb.d_len, add, cap);
+  const int64_t ntiles = (len + kScanBlock - 1) / kScanBlock;
+  unsigned long long* W = words + blockIdx.y * wstride;
+  const unsigned long long ep = (unsigned long long)epoch << 32;
+  __shared__ int wsum[kSortThreads / 64];
+  __shared__ int s_prefix;
+  const int lane = threadIdx.x & 63;
+  if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0 && jb.total) *jb.total = 0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t base = tile * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = base + j < len ? jb.in[base + j] : 0;
+      sum += v[j];
+    }
+    int total;
+    const int ex = block_exclusive_scan(sum, wsum, total);
+    if (threadIdx.x == 0)
+      chain_store(&W[tile], (tile == 0 ? kChainIncl : kChainSum) | ep | (unsigned)total);
+    if (threadIdx.x < 64) {
+      int prefix = 0;
+      if (tile > 0) {
+        int64_t newest = tile - 1;  // the window: tiles newest - 63 .. newest, lane l on newest - l
+        int spins = 0;
+        for (;;) {
+          const int64_t q = newest - lane;
+          unsigned long long w = q >= 0 ? chain_load(&W[q]) : (kChainIncl | ep);
+          if ((w & kChainEpoch) != ep) w = 0;
+          const uint64_t incl = __ballot((w & kChainIncl) != 0);
+          const uint64_t none = __ballot((w & (kChainIncl | kChainSum)) == 0);
+          const int stop = incl ? __builtin_ctzll(incl) : 64;  // the nearest inclusive prefix
+          const uint64_t upto = stop >= 63 ? ~0ull : ((2ull << stop) - 1);
+          if (none & upto) {  // a tile up to it has not published yet
+            if (++spins > kChainSpins) {
+              if (lane == 0) atomicCAS(&h->err, 0, HULL_EINTERNAL);
+              break;
+            }
+            continue;
+          }
+          int x = lane <= stop ? (int)(unsigned)(w & 0xffffffffull) : 0;
+          for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+          prefix += x;
+          if (stop < 64) break;
+          newest -= 64;  // 64 sums: the prefix lies further back
+        }
+      }
+      if (threadIdx.x == 0) {
+        s_prefix = prefix;
+        if (tile > 0) chain_store(&W[tile], kChainIncl | ep | (unsigned)(prefix + total));
+      }
+    }
+    __syncthreads();
+    int run = s_prefix + ex;
+    for (int j = 0; j < kScanItems; ++j) {
+      if (base + j < len) jb.out[base + j] = run;
+      run += v[j];
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0 && jb.total) *jb.total = s_prefix + total;
+    __syncthreads();  // s_prefix is rewritten by the next tile
+  }
+}
+
+int32_t exclusive_scan_chained(const ScanJobs& J, int add, int64_t cap, unsigned long long* words,
+                               int64_t wstride, unsigned epoch, Header* h, hipStream_t s) {
+  if (cap <= 0 || J.count <= 0) return HULL_OK;
+  const int64_t blocks = (cap + kScanBlock - 1) / kScanBlock;
+  if (J.count > kMaxScanJobs || blocks > wstride || epoch == 0 || epoch > 0x3fffffffu)
+    return HULL_EINVAL;
+  const unsigned grid = (unsigned)(blocks < kScanDevGrid ? blocks : kScanDevGrid);
+  hipLaunchKernelGGL(k_scan_chained, dim3(grid, J.count), dim3(kSortThreads), 0, s, J, add, cap,
+                     words, wstride, epoch, h);
+  HULL_LAUNCH_CHECK();
+  return HULL_OK;
+}
+
+__global__ void __launch_bounds__(256) k_zero_words(unsigned long long* w, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = 0;
+}
+
+void zero_words(unsigned long long* w, int64_t count, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t b = (count + 255) / 256;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, w,
+                     count);
+}
+
 int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_t* partials,
                                  hipStream_t s) {
   if (cap <= 0 || J.count <= 0) return HULL_OK;
