@@ -84,7 +84,7 @@ struct __align__(16) Entry {
 
 // Offsets (bytes) of every workspace region for n points in H hulls.
 struct Plan {
-  size_t header, keys0, vals0, keys1, vals1, counts, partials, pts, hid, off1;
+  size_t header, keys0, vals0, keys1, vals1, counts, pts, hid, off1;
   size_t pv0[2], nx0[2], lk[2];
   size_t ev[2][2], len[2][2];  // [run][buffer]
   // the level schedule (merge list, trailing blocks)
@@ -104,7 +104,7 @@ struct Plan {
   // face counts of the hulls of a batch
   size_t fcnt;
   size_t total;
-  int64_t n, H, tiles, count_len, partial_len, mcap, seg_cap;
+  int64_t n, H, tiles, count_len, mcap, seg_cap;
 };
 
 // min_seg: the smallest walk segment (child events) the plan must hold;
@@ -153,35 +153,34 @@ template <class InT, class PT>
 int32_t sort_points(const InT* d_xyz, int64_t n, const int64_t* hull_off, int64_t H, char* ws,
                     const Plan& pl, hipStream_t s);
 
-// Exclusive scans of int32 (in place allowed).  The second form reads its
-// length from device memory: len = *d_len + add, never more than cap.
-int32_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t len, int32_t* partials,
-                           hipStream_t s);
-int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
-                           int64_t cap, int32_t* partials, hipStream_t s);
-
-// Several such scans (same add and cap, each its own device length) in one
-// set of launches.  partials must hold kMaxScanJobs * (cap / 4096 + 2) ints.
+// Exclusive scans of int32 (in place allowed), each in one launch (a chained
+// scan): up to kMaxScanJobs arrays of the same add and cap, each of a length
+// read from device memory (len = *d_len + add, never more than cap; a null
+// d_len: cap itself).  Job j publishes one status word per tile at words +
+// j * wstride (wstride >= cap / 4096 rounded up); epoch (1 .. 2^30 - 1) tells
+// this scan's words from those of earlier scans that used the same words,
+// which must hold zero or another epoch.
 constexpr int kMaxScanJobs = 8;
-constexpr int kChainJobs = 16;  // job slots of one parallel level's one-launch scans
+constexpr int kChainJobs = 16;  // job slots of the status words (a parallel level's scans)
 struct ScanJob {
   const int32_t* in;
   int32_t* out;
   const int32_t* d_len;
-  int32_t* total;  // if set: receives the sum of in[0, *d_len) (the scan's total)
+  int32_t* total;  // if set: receives the sum of the scanned entries (the scan's total)
 };
 struct ScanJobs {
   ScanJob j[kMaxScanJobs];
   int count;
 };
-int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_t* partials,
-                                 hipStream_t s);
-// The same scans in one launch (a chained scan).  Job j publishes one status
-// word per tile at words + j * wstride (wstride >= cap / 4096 rounded up);
-// epoch (1 .. 2^30 - 1) tells this scan's words from those of earlier scans
-// that used the same words, which must hold zero or another epoch.
 int32_t exclusive_scan_chained(const ScanJobs& J, int add, int64_t cap, unsigned long long* words,
                                int64_t wstride, unsigned epoch, Header* h, hipStream_t s);
+// One array of host-known length (slot 0 of the words).
+int32_t scan_chained_i32(const int32_t* in, int32_t* out, int64_t len, unsigned long long* words,
+                         int64_t wstride, unsigned epoch, Header* h, hipStream_t s);
+// Epochs of the one-launch scans of a call: the sort's passes 1..8, level k's
+// scans 8k + 1..7, the face offsets kChainEpochFaces.  The sort clears the
+// words at the start of every call.
+constexpr unsigned kChainEpochFaces = 8 * 28 + 1;
 // Zero count 64-bit words (a kernel: capturable).
 void zero_words(unsigned long long* w, int64_t count, hipStream_t s);
 

@@ -398,6 +398,6 @@ struct ParLevel {
 };
 
 template <class PT>
-int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s);
+int32_t parallel_level(const ParLevel& P, hipStream_t s);
 
 }  // namespace hull

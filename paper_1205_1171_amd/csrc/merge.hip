@@ -796,11 +796,10 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
   P.seg_events = opt.seg;
   P.seg_cap = pl.seg_cap;
   P.ecap = 2 * n;
+  // the call's one-launch scans tell their status words apart by epoch (the
+  // sort cleared the words at the start of the call)
   P.chain_words = (unsigned long long*)(ws + pl.chain_words);
   P.chain_stride = pl.chain_stride;
-  // the one-launch scans of the parallel levels tell their status words
-  // apart by level within the call: clear the words left by an earlier call
-  if (opt.serial_max < levels) zero_words(P.chain_words, kChainJobs * P.chain_stride, s);
   for (int r = 0; r < 2; ++r) {
     bool on = r == 0 ? lower : upper;
     RunPtrs& R = A.run[r];
@@ -855,7 +854,6 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       hipLaunchKernelGGL(k_init_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0,
                          (int*)(ws + pl.len[r][0]), Q.claimR, Q.claimL, n);
   }
-  int32_t* partials = (int32_t*)(ws + pl.partials);
   int buf = 0;
   const unsigned hgrid = grid_for(S.H + 1, 1024);
   for (int k = 1; k <= levels; ++k) {
@@ -878,8 +876,11 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
                          n);
     } else {
       hipLaunchKernelGGL(k_sched_count, dim3(hgrid), dim3(256), 0, s, S, k, mcnt, tcnt);
-      rc = exclusive_scan_i32(mcnt, S.moff, S.H + 1, partials, s);
-      if (!rc) rc = exclusive_scan_i32(tcnt, S.toff, S.H + 1, partials, s);
+      rc = scan_chained_i32(mcnt, S.moff, S.H + 1, P.chain_words, P.chain_stride,
+                            (unsigned)(8 * k + 6), h, s);
+      if (!rc)
+        rc = scan_chained_i32(tcnt, S.toff, S.H + 1, P.chain_words, P.chain_stride,
+                              (unsigned)(8 * k + 7), h, s);
       if (rc) return rc;
       hipLaunchKernelGGL(k_sched_fill, dim3(grid_for(std::min<int64_t>(pl.mcap, n / A.width + S.H + 1))),
                          dim3(256), 0, s, S, k);
@@ -946,7 +947,7 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     } else {
       P.k = k;
       P.run[0].stamp = P.run[1].stamp = k;
-      rc = parallel_level<PT>(P, partials, s);
+      rc = parallel_level<PT>(P, s);
       if (rc) return rc;
     }
     if (events) (void)hipEventRecord(events[2 * k + 1], s);
@@ -982,10 +983,10 @@ static int32_t extract(const Sched& S, char* ws, const Plan& pl, hipStream_t s, 
   X.face_off = d_face_off;
   X.info = d_info;
   X.h = (const Header*)(ws + pl.header);
-  int32_t* partials = (int32_t*)(ws + pl.partials);
   hipLaunchKernelGGL(k_face_count, dim3(grid_for(S.H + 1, 1024)), dim3(256), 0, s, X);
   if (S.H > 1) {  // one hull: k_face_count writes the offsets themselves
-    int32_t rc = exclusive_scan_i32(X.fcnt, X.fcnt, S.H + 1, partials, s);
+    int32_t rc = scan_chained_i32(X.fcnt, X.fcnt, S.H + 1, (unsigned long long*)(ws + pl.chain_words),
+                                  pl.chain_stride, kChainEpochFaces, (Header*)(ws + pl.header), s);
     if (rc) return rc;
   }
   hipLaunchKernelGGL(k_extract<PT>, dim3(grid_for(std::max<int64_t>(cap, S.H + 1), 2048)), dim3(256), 0,

@@ -732,8 +732,7 @@ static int32_t chained(const ParLevel& P, const ScanJobs& J, int slot, int site,
 }
 
 template <class PT>
-int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
-  (void)partials;
+int32_t parallel_level(const ParLevel& P, hipStream_t s) {
   const dim3 g2(kStrideBlocks, 2), b256(256);
   hipLaunchKernelGGL(k_par_prep, g2, b256, 0, s, P);
   // per merge: child events, walk segments (length: merges + 1)
@@ -763,7 +762,7 @@ int32_t parallel_level(const ParLevel& P, int32_t* partials, hipStream_t s) {
   return HULL_OK;
 }
 
-template int32_t parallel_level<int4>(const ParLevel&, int32_t*, hipStream_t);
-template int32_t parallel_level<WPt>(const ParLevel&, int32_t*, hipStream_t);
+template int32_t parallel_level<int4>(const ParLevel&, hipStream_t);
+template int32_t parallel_level<WPt>(const ParLevel&, hipStream_t);
 
 }  // namespace hull

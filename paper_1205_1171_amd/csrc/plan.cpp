@@ -9,7 +9,7 @@ static thread_local int32_t g_last_hip_error = 0;
 
 void note_hip_error(hipError_t e) { g_last_hip_error = (int32_t)e; }
 
-static int64_t scan_partials_needed(int64_t len) { return (len + kScanBlock - 1) / kScanBlock; }
+static int64_t scan_tiles(int64_t len) { return (len + kScanBlock - 1) / kScanBlock; }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -26,7 +26,6 @@ Plan make_plan(int64_t n, int64_t H, int min_seg, int pt_bytes) {
   // walk segments of one level: sum over merges of 1 + events / G, events <= 2n
   p.seg_cap = p.mcap + (2 * nn) / std::max(min_seg, 1) + 1;
   int64_t longest = std::max<int64_t>({p.count_len, 2 * nn + 1, p.seg_cap + 1, hh + 1});
-  p.partial_len = kMaxScanJobs * (scan_partials_needed(longest) + 2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -34,8 +33,7 @@ Plan make_plan(int64_t n, int64_t H, int min_seg, int pt_bytes) {
     return o;
   };
   p.header = take(sizeof(Header));
-  p.partials = take(p.partial_len * 4);
-  p.chain_stride = scan_partials_needed(longest) + 1;
+  p.chain_stride = scan_tiles(longest) + 1;
   p.chain_words = take(kChainJobs * p.chain_stride * sizeof(unsigned long long));
   p.pts = take(nn * (size_t)pt_bytes);
   p.off1 = take(2 * sizeof(int64_t));

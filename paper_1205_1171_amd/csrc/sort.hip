@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of int32 (three phases: tile sums, scan of the sums, tiles).
+// Exclusive scans of int32 (one launch each: a chained scan).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int block_exclusive_scan(int x, int* lds_wave, int& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -234,134 +234,16 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int* lds_wave, int& t
   return before + incl - x;
 }
 
-__global__ void __launch_bounds__(kSortThreads)
-    k_scan_tile_sums(const int32_t* __restrict__ in, int64_t len, int32_t* __restrict__ sums) {
-  __shared__ int wsum[kSortThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  int s = 0;
-  for (int j = 0; j < kScanItems; ++j)
-    if (base + j < len) s += in[base + j];
-  int total;
-  block_exclusive_scan(s, wsum, total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(kSortThreads) k_scan_sums(int32_t* sums, int64_t nsums) {
-  __shared__ int wsum[kSortThreads / 64];
-  int carry = 0;
-  for (int64_t b = 0; b < nsums; b += kSortThreads) {
-    int64_t q = b + threadIdx.x;
-    int x = q < nsums ? sums[q] : 0;
-    int total;
-    int ex = block_exclusive_scan(x, wsum, total);
-    if (q < nsums) sums[q] = carry + ex;
-    carry += total;
-  }
-}
-
-__global__ void __launch_bounds__(kSortThreads)
-    k_scan_tiles(const int32_t* __restrict__ in, int64_t len, const int32_t* __restrict__ sums,
-                 int32_t* __restrict__ out) {
-  __shared__ int wsum[kSortThreads / 64];
-  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-  for (int j = 0; j < kScanItems; ++j) {
-    v[j] = base + j < len ? in[base + j] : 0;
-    s += v[j];
-  }
-  int total;
-  int run = block_exclusive_scan(s, wsum, total) + sums[blockIdx.x];
-  for (int j = 0; j < kScanItems; ++j) {
-    if (base + j < len) out[base + j] = run;
-    run += v[j];
-  }
-}
-
-int32_t exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t len, int32_t* partials,
-                           hipStream_t s) {
-  if (len <= 0) return HULL_OK;
-  int64_t blocks = (len + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, in, len,
-                     partials);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kSortThreads), 0, s, partials, blocks);
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)blocks), dim3(kSortThreads), 0, s, in, len,
-                     partials, out);
-  HULL_LAUNCH_CHECK();
-  return HULL_OK;
-}
-
-
-// Scan with a length read from device memory (grids sized for the cap;
-// blocks past the actual length exit at once).
+// The length of a scan: read from device memory (+ add, at most cap), or cap
+// itself for a length known on the host.
 __device__ __forceinline__ int64_t dev_len(const int32_t* d_len, int add, int64_t cap) {
+  if (!d_len) return cap;  // a length known on the host: cap itself
   int64_t L = (int64_t)(*d_len) + add;
   return L < 0 ? 0 : (L > cap ? cap : L);
 }
 
-// Up to kMaxScanJobs scans of device-given lengths in the same three
-// launches (blockIdx.y = job); job j keeps its tile sums at partials +
-// j * pstride.
-__global__ void __launch_bounds__(kSortThreads)
-    k_scan_tile_sums_dev(ScanJobs J, int add, int64_t cap, int64_t pstride, int32_t* partials) {
-  const ScanJob& jb = J.j[blockIdx.y];
-  const int64_t len = dev_len(jb.d_len, add, cap);
-  __shared__ int wsum[kSortThreads / 64];
-  for (int64_t tile = blockIdx.x; tile * kScanBlock < len; tile += gridDim.x) {
-    const int64_t base = tile * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-    int s = 0;
-    for (int j = 0; j < kScanItems; ++j)
-      if (base + j < len) s += jb.in[base + j];
-    int total;
-    block_exclusive_scan(s, wsum, total);
-    if (threadIdx.x == 0) partials[blockIdx.y * pstride + tile] = total;
-  }
-}
-
-__global__ void __launch_bounds__(kSortThreads)
-    k_scan_sums_dev(ScanJobs J, int add, int64_t cap, int64_t pstride, int32_t* partials) {
-  const ScanJob& jb = J.j[blockIdx.x];
-  const int64_t len = dev_len(jb.d_len, add, cap);
-  const int64_t nsums = (len + kScanBlock - 1) / kScanBlock;
-  int32_t* sums = partials + blockIdx.x * pstride;
-  __shared__ int wsum[kSortThreads / 64];
-  int carry = 0;
-  for (int64_t b = 0; b < nsums; b += kSortThreads) {
-    int64_t q = b + threadIdx.x;
-    int x = q < nsums ? sums[q] : 0;
-    int total;
-    int ex = block_exclusive_scan(x, wsum, total);
-    if (q < nsums) sums[q] = carry + ex;
-    carry += total;
-  }
-  // the entries past *d_len (add of them) are zero: carry is the total
-  if (jb.total && threadIdx.x == 0) *jb.total = carry;
-}
-
-__global__ void __launch_bounds__(kSortThreads)
-    k_scan_tiles_dev(ScanJobs J, int add, int64_t cap, int64_t pstride,
-                     const int32_t* __restrict__ partials) {
-  const ScanJob& jb = J.j[blockIdx.y];
-  const int64_t len = dev_len(jb.d_len, add, cap);
-  __shared__ int wsum[kSortThreads / 64];
-  for (int64_t tile = blockIdx.x; tile * kScanBlock < len; tile += gridDim.x) {
-    const int64_t base = tile * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-    int v[kScanItems];
-    int s = 0;
-    for (int j = 0; j < kScanItems; ++j) {
-      v[j] = base + j < len ? jb.in[base + j] : 0;
-      s += v[j];
-    }
-    int total;
-    int run = block_exclusive_scan(s, wsum, total) + partials[blockIdx.y * pstride + tile];
-    for (int j = 0; j < kScanItems; ++j) {
-      if (base + j < len) jb.out[base + j] = run;
-      run += v[j];
-    }
-  }
-}
-
-// The same scans in one launch.  Tile t of a job (blocks stride over the
+// Scans of up to kMaxScanJobs arrays (blockIdx.y = job), one launch.  Tile t
+// of a job (blocks stride over the
 // tiles) publishes its sum, then finds the sum of all tiles before it by
 // looking back over their published words, 64 at a time, until one holds an
 // inclusive prefix (a chained scan with decoupled look-back), publishes its
@@ -463,6 +345,15 @@ int32_t exclusive_scan_chained(const ScanJobs& J, int add, int64_t cap, unsigned
   return HULL_OK;
 }
 
+int32_t scan_chained_i32(const int32_t* in, int32_t* out, int64_t len, unsigned long long* words,
+                         int64_t wstride, unsigned epoch, Header* h, hipStream_t s) {
+  if (len <= 0) return HULL_OK;
+  ScanJobs J{};
+  J.j[0] = ScanJob{in, out, nullptr, nullptr};
+  J.count = 1;
+  return exclusive_scan_chained(J, 0, len, words, wstride, epoch, h, s);
+}
+
 __global__ void __launch_bounds__(256) k_zero_words(unsigned long long* w, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -474,33 +365,6 @@ void zero_words(unsigned long long* w, int64_t count, hipStream_t s) {
   const int64_t b = (count + 255) / 256;
   hipLaunchKernelGGL(k_zero_words, dim3((unsigned)(b < 1024 ? b : 1024)), dim3(256), 0, s, w,
                      count);
-}
-
-int32_t exclusive_scan_dev_multi(const ScanJobs& J, int add, int64_t cap, int32_t* partials,
-                                 hipStream_t s) {
-  if (cap <= 0 || J.count <= 0) return HULL_OK;
-  if (J.count > kMaxScanJobs) return HULL_EINVAL;
-  const int64_t blocks = (cap + kScanBlock - 1) / kScanBlock;
-  const int64_t pstride = blocks + 1;
-  // the lengths are known only on the device: a capped grid strides over
-  // the tiles, so a short scan under a large cap launches few idle blocks
-  const unsigned grid = (unsigned)(blocks < kScanDevGrid ? blocks : kScanDevGrid);
-  hipLaunchKernelGGL(k_scan_tile_sums_dev, dim3(grid, J.count), dim3(kSortThreads), 0, s, J, add,
-                     cap, pstride, partials);
-  hipLaunchKernelGGL(k_scan_sums_dev, dim3(J.count), dim3(kSortThreads), 0, s, J, add, cap,
-                     pstride, partials);
-  hipLaunchKernelGGL(k_scan_tiles_dev, dim3(grid, J.count), dim3(kSortThreads), 0, s, J, add, cap,
-                     pstride, partials);
-  HULL_LAUNCH_CHECK();
-  return HULL_OK;
-}
-
-int32_t exclusive_scan_dev(const int32_t* in, int32_t* out, const int32_t* d_len, int add,
-                           int64_t cap, int32_t* partials, hipStream_t s) {
-  ScanJobs J{};
-  J.j[0] = ScanJob{in, out, d_len, nullptr};
-  J.count = 1;
-  return exclusive_scan_dev_multi(J, add, cap, partials, s);
 }
 
 void init_header(Header* h, hipStream_t s) {
@@ -517,7 +381,6 @@ int32_t sort_points(const InT* d_xyz, int64_t n, const int64_t* hull_off, int64_
   B.vals[0] = (int32_t*)(ws + pl.vals0);
   B.vals[1] = (int32_t*)(ws + pl.vals1);
   int32_t* counts = (int32_t*)(ws + pl.counts);
-  int32_t* partials = (int32_t*)(ws + pl.partials);
   int32_t* hid = nullptr;
   int hull_passes = 0;
   if (hull_off && H > 1) {
@@ -527,6 +390,10 @@ int32_t sort_points(const InT* d_xyz, int64_t n, const int64_t* hull_off, int64_
     hull_passes = (hb + kRadixBits - 1) / kRadixBits;
   }
   const int tiles = (int)pl.tiles;
+  // the status words of the call's one-launch scans start from zero here:
+  // the sort's passes use epochs 1..8, the merge levels higher ones
+  unsigned long long* words = (unsigned long long*)(ws + pl.chain_words);
+  zero_words(words, kChainJobs * pl.chain_stride, s);
   unsigned eg = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
   if (eg < 1) eg = 1;
   hipLaunchKernelGGL(k_extent<InT>, dim3(eg), dim3(256), 0, s, d_xyz, n, h);
@@ -537,7 +404,8 @@ int32_t sort_points(const InT* d_xyz, int64_t n, const int64_t* hull_off, int64_
     for (int d = 0; d < npass; ++d) {
       hipLaunchKernelGGL(k_radix_hist<InT>, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
                          kind, d, tiles, counts, h);
-      int32_t rc = exclusive_scan_i32(counts, counts, pl.count_len, partials, s);
+      int32_t rc = scan_chained_i32(counts, counts, pl.count_len, words, pl.chain_stride,
+                                    (unsigned)(1 + kind * 4 + d), h, s);
       if (rc) return rc;
       hipLaunchKernelGGL(k_radix_scatter<InT>, dim3(tiles), dim3(kSortThreads), 0, s, d_xyz, B, hid, n,
                          kind, d, tiles, counts, h);
