@@ -180,7 +180,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out);
 
 /* Bytes of device workspace for hull_full_batched over H hulls of
  * total_points points in all (host, synchronous).  total_points is at most
- * 2^28 (whose workspace, about 830 bytes per point, fits one GPU's memory);
+ * 2^28 (whose workspace, about 924 bytes per point, fits one GPU's memory);
  * more returns HULL_EINVAL, as does hull_full_batched. */
 int32_t hull_workspace_bytes_batched(int64_t total_points, int64_t H, size_t* bytes);
 

@@ -10,7 +10,7 @@ namespace hull {
 
 constexpr int kNil = -1;
 constexpr int64_t kMaxN = int64_t(1) << 26;      // points of one hull
-// points of a batch: the workspace of 2^28 points (about 830 bytes per
+// points of a batch: the workspace of 2^28 points (about 924 bytes per
 // point) still fits the 288 GB of one MI355X
 constexpr int64_t kMaxTotal = int64_t(1) << 28;
 constexpr int32_t kMaxCoord = 1 << 29;
@@ -25,7 +25,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanBlock = kSortThreads * kScanItems;
 constexpr int kStrideBlocks = 1024;  // grid of the grid-stride kernels
 constexpr int kScanDevGrid = 128;    // tile blocks per job of a device-length scan
-constexpr int kSegKeep = 2;  // bridge events a walk segment keeps from its counting pass
+constexpr int kSegKeep = 4;  // bridge events a walk segment keeps from its counting pass
 constexpr int kMinWalkSegment = 4;  // fewest child events per walk segment
 constexpr int kWorkBins = 1024;     // child-event counts told apart when ordering merges
 
