@@ -7,13 +7,17 @@ value = Mpoints/s = n / (time per step).
 
 Also reported on the same line:
   roofline        the merge kernel with the largest share of the step (the
-                  lane-serial k_merge_level, the lane-group k_merge_wave or
-                  the LDS-staged k_merge_level_lds, whichever takes the most
+                  lane-serial k_merge_level_lk with its links in LDS, or
+                  k_merge_level, the lane-group k_merge_wave or the
+                  LDS-staged k_merge_level_lds, whichever takes the most
                   time over its levels): algorithmic bytes per launch (from
                   the oracle's per-level counters: 4 B per event read, 4 B
                   per event written, 28 B per point touched) over its average
                   launch time, measured with HIP events recorded around each
-                  of its launches on the library's stream in the timed steps;
+                  of its launches on the library's stream in the timed steps,
+                  and the HBM traffic per launch that rocprofv3's FETCH_SIZE
+                  and WRITE_SIZE counters read for it (profiles/, while the
+                  merge sources are the ones profiled);
   levels          the same figure for every merge level (the parallel levels
                   are several kernels each, timed as a whole);
   other_single_hulls  Mpoints/s and bit-exact flags on n = 4096 and the
