@@ -152,7 +152,9 @@ int32_t hull_full_noalloc(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int
  *   wave_from      lane-serial levels from this one on run one merge per
  *                  group of wave_lanes lanes instead of one per lane (the
  *                  six candidates of an iteration on six lanes, child movies
- *                  through LDS); 0: the default (8), negative: no level
+ *                  through LDS); 0: the default (level 5 for calls of up to
+ *                  2^18 points in all, one level later per doubling, level 8
+ *                  from 2^21 points), negative: no level
  *   wave_lanes     lanes per merge at level wave_from: 8, 16, 32 or 64,
  *                  doubling with every level above (merges halve), up to 64
  *                  (0: the default, 8)
@@ -167,7 +169,8 @@ typedef struct hull_schedule_t {
 } hull_schedule_t;
 
 /* The schedule the library uses when a call passes none (or leaves a field
- * at its default): the built-in defaults, overridden by the environment
+ * at its default; wave_from as for the largest calls, 2^21 points and more):
+ * the built-in defaults, overridden by the environment
  * variables HULL_SERIAL_LEVELS, HULL_WALK_SEGMENT, HULL_WAVE_LEVEL and
  * HULL_WAVE_LANES when set.  On output, fused_levels is the number of lowest
  * lane-serial levels that stage each merge's points and links in LDS (a

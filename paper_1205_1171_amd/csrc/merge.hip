@@ -756,12 +756,23 @@ struct Opts {
   int64_t order_min;  // ... when the level bounds at least this many merges
 };
 
-static Opts resolve(const hull_schedule_t* sc) {
+// The first lane-group level when the caller gives none: lane groups pay
+// once a level's merges are too few to fill the chip one lane each (they
+// then get several lanes), so the fewer points a call has in all, the lower
+// the level -- level 5 up to 2^18 points, one level later per doubling, level
+// 8 from 2^21 (measured on cubes and spheres of 2^11..2^20 points and on
+// the n = 2^24 workload).
+static int default_wave_level(int64_t total) {
+  return std::min(8, std::max(kLdsLevels + 1, levels_for(total) - 13));
+}
+
+static Opts resolve(const hull_schedule_t* sc, int64_t total) {
   Opts o;
   o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 10);
   o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 4);
   if (o.seg < kMinWalkSegment) o.seg = kMinWalkSegment;
-  const int wf = sc && sc->wave_from != 0 ? sc->wave_from : env_int("HULL_WAVE_LEVEL", 8);
+  const int wf = sc && sc->wave_from != 0 ? sc->wave_from
+                                          : env_int("HULL_WAVE_LEVEL", default_wave_level(total));
   o.wave_from = wf > 0 ? std::max(wf, kLdsLevels + 1) : 0;
   const int wl = sc && sc->wave_lanes > 0 ? sc->wave_lanes : env_int("HULL_WAVE_LANES", 8);
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
@@ -1004,7 +1015,7 @@ static int32_t hull_runs_t(const InT* d_xyz, int64_t n, int32_t* d_faces, int64_
   const int L = levels_for(n);
   if (events && nevents < 2 * L + 3) return HULL_EINVAL;
   hipEvent_t* ev = (hipEvent_t*)events;
-  const Opts opt = resolve(nullptr);
+  const Opts opt = resolve(nullptr, n);
   Plan pl = make_plan(n, 1, opt.seg, (int)sizeof(PT));
   if (ws_bytes < pl.total) return HULL_EWORKSPACE;
   char* ws = (char*)d_ws;
@@ -1055,7 +1066,7 @@ int32_t batched(const int32_t* d_xyz, const int64_t* d_off, const int64_t* h_off
   const int64_t n = h_off[H];
   if (h_off[0] != 0 || n < 0 || n > kMaxTotal || (n > 0 && !d_xyz) || cap < 2 * n)
     return HULL_EINVAL;
-  const Opts opt = resolve(sched);
+  const Opts opt = resolve(sched, n);
   int L = 0;
   for (int64_t q = 0; q < H; ++q) {
     const int64_t nh = h_off[q + 1] - h_off[q];
@@ -1090,7 +1101,7 @@ int32_t movies(const int32_t* d_xyz, int64_t n, int32_t run, int32_t level, int3
   if (n < 1 || n > kMaxN || !d_xyz || !d_ev || !d_block_len || !d_order || !d_info || !d_ws ||
       (run != 0 && run != 1))
     return HULL_EINVAL;
-  const Opts opt = resolve(nullptr);
+  const Opts opt = resolve(nullptr, n);
   Plan pl = make_plan(n, 1, opt.seg);
   if (ws_bytes < pl.total) return HULL_EWORKSPACE;
   char* ws = (char*)d_ws;
@@ -1145,7 +1156,7 @@ int32_t hull_workspace_bytes(int64_t n, int32_t flags, size_t* bytes) {
 
 int32_t hull_schedule_defaults(hull_schedule_t* out) {
   if (!out) return HULL_EINVAL;
-  const hull::Opts o = hull::resolve(nullptr);
+  const hull::Opts o = hull::resolve(nullptr, hull::kMaxN);
   out->serial_levels = o.serial_max;
   out->walk_segment = o.seg;
   out->fused_levels = o.lds_levels;
