@@ -20,7 +20,7 @@ CACHE = os.path.join(HERE, "tuned_schedules.json")
 
 SERIAL_LEVELS = (8, 9, 10, 11, 12, 13, 14, 99)
 WALK_SEGMENTS = (8, 16, 32)
-WAVE_LEVELS = (-1, 7, 8, 9)  # -1: no lane groups
+WAVE_LEVELS = (-1, 5, 6, 7, 8, 9)  # -1: no lane groups
 WAVE_LANES = 8
 
 
