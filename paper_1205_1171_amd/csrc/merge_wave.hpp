@@ -25,6 +25,45 @@
 
 namespace hull {
 
+// x of the lane CTRL names, through a data-parallel move (a register
+// operation: no LDS round trip); CTRL: quad permutation or half-row mirror.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Minimum over each aligned group of 8 lanes, on all 8 lanes: the quad
+// permutations [1,0,3,2] and [2,3,0,1], then the half-row mirror (lane i and
+// lane 7 - i), which pairs the two quads.
+__device__ inline double min8(double x) {
+  x = fmin(x, dpp_f64<0xB1>(x));
+  x = fmin(x, dpp_f64<0x4E>(x));
+  return fmin(x, dpp_f64<0x141>(x));
+}
+
+// x of lane `src` of the caller's group of G lanes (src the same on every lane
+// of the group): a lane read into a scalar register when the group is the
+// whole wave, else a permute through LDS.
+template <int G>
+__device__ inline int group_bcast(int x, int src) {
+  if constexpr (G == 64) return __builtin_amdgcn_readlane(x, __builtin_amdgcn_readfirstlane(src));
+  else return __shfl(x, src, G);
+}
+template <int G>
+__device__ inline double group_bcast(double x, int src) {
+  if constexpr (G == 64) {
+    const long long b = __double_as_longlong(x);
+    const int s = __builtin_amdgcn_readfirstlane(src);
+    const int lo = __builtin_amdgcn_readlane((int)b, s), hi = __builtin_amdgcn_readlane((int)(b >> 32), s);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  } else {
+    return __shfl(x, src, G);
+  }
+}
+
 // With LDSL the merge's working links sit in LDS as block-local int16 ranks
 // (dynamic LDS: 256 / G merges per block x width link pairs of 4 bytes),
 // loaded by the group from the -inf links; without, in the level's global
@@ -177,9 +216,8 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
     // valid candidate is known to be later; else exact comparisons
     const bool mine = lane < 6 && valid;
     const bool num = mine && c.st == c.st;
-    double mn = num ? c.st : __builtin_inf();
-    for (int o = 1; o < 8; o <<= 1) mn = fmin(mn, __shfl_xor(mn, o, G));
-    mn = __shfl(mn, 0, G);
+    // (lanes 0..7 of the group hold the minimum; only lanes 0..5 use it)
+    const double mn = min8(num ? c.st : __builtin_inf());
     const bool amb = mine && (!num || !(c.st - mn > 0x1p-23 * (fabs(c.st) + fabs(mn))));
     const uint64_t mask = (__ballot(amb) >> gshift) & 0x3Full;
     if (!mask) break;
@@ -199,9 +237,10 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
         if (ev_cmp(pts, cx, cw, zs) < 0) win = x;
       }
     }
-    const int ba = __shfl(c.t.a, win, G), bw = __shfl(c.t.w, win, G), bb = __shfl(c.t.b, win, G);
-    const int bk = __shfl(c.kind, win, G);
-    const double bs = __shfl(c.st, win, G);
+    const int ba = group_bcast<G>(c.t.a, win), bw = group_bcast<G>(c.t.w, win),
+              bb = group_bcast<G>(c.t.b, win);
+    const int bk = group_bcast<G>(c.kind, win);
+    const double bs = group_bcast<G>(c.st, win);
     T.t = Tri{ba, bw, bb};
     T.st = bs;
     T.kind = bk;
