@@ -177,7 +177,10 @@ typedef struct hull_schedule_t {
  * separate kernel from the other lane-serial levels; default 3, at most 4,
  * environment HULL_LDS_LEVELS).  Above them, lane-serial merges of blocks up
  * to 128 points and lane-group merges keep only their working links in LDS
- * (HULL_LDS_LINKS=0: in global memory).  None of this changes a result.
+ * (HULL_LDS_LINKS=0: in global memory), except on lane-group levels of at
+ * most 1024 merges in all (environment HULL_PTS_LDS_MERGES), where a merge's
+ * points join its links in LDS when a workgroup's share fits.  None of this
+ * changes a result.
  * Host, synchronous. */
 int32_t hull_schedule_defaults(hull_schedule_t* out);
 

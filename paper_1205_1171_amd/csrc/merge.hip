@@ -318,6 +318,24 @@ __global__ void __launch_bounds__(256) k_merge_level(LevelArgs A) {
 // branches.
 constexpr int kOrderFromLevel = 6;
 constexpr int64_t kOrderMinMerges = 32768;
+// Lane-group levels of at most this many merges (both runs) hold the merge's
+// points in LDS as well as its links.
+constexpr int kPtsLdsMerges = 1024;
+
+// Bytes of LDS one workgroup may use on the current device (looked up once
+// per device).
+static int64_t max_lds_bytes() {
+  static int64_t cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 65536;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
 
 // Work order of a level's merges.  The lanes of a wavefront run their merges
 // in lockstep, so a wave lasts as long as its longest merge; listing the
@@ -754,6 +772,8 @@ struct Opts {
                    // above them, the links alone)
   int order_from;     // lane-serial levels from this one list their merges in work order
   int64_t order_min;  // ... when the level bounds at least this many merges
+  int64_t pts_lds_merges;  // lane-group levels of at most this many merges (both runs
+                           // together) hold the points in LDS too, where they fit
 };
 
 // The first lane-group level when the caller gives none: lane groups pay
@@ -780,6 +800,7 @@ static Opts resolve(const hull_schedule_t* sc, int64_t total) {
   o.lds_levels = std::min(std::max(env_int("HULL_LDS_LEVELS", 3), 0), kLdsLevels);
   o.order_from = env_int("HULL_ORDER_LEVEL", kOrderFromLevel);
   o.order_min = std::max(env_int("HULL_ORDER_MIN", (int)kOrderMinMerges), 0);
+  o.pts_lds_merges = std::max(env_int("HULL_PTS_LDS_MERGES", kPtsLdsMerges), 0);
   return o;
 }
 
@@ -876,7 +897,15 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     const int lanes = wave ? std::min(64, opt.wave_lanes << std::min(k - opt.wave_from, 3)) : 0;
     const bool lds_lane = serial && k > opt.lds_levels && !wave && opt.lds_links &&
                           A.width <= kLinkLdsLane;
-    const bool lds_group = wave && opt.lds_links &&
+    const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
+    // points in LDS as well: levels of few merges (each iteration of a long
+    // merge then waits on LDS rather than on a cache), when a block fits
+    const bool pts_lds = wave && opt.lds_links && 2 * bound <= opt.pts_lds_merges &&
+                         A.width <= 32767 &&
+                         (64 / lanes) * A.width * (int64_t)(sizeof(LinkPair<short>) + sizeof(PT)) +
+                                 (int64_t)sizeof(Event) * 128 <=
+                             max_lds_bytes();
+    const bool lds_group = wave && opt.lds_links && !pts_lds &&
                            (256 / lanes) * A.width * (int64_t)sizeof(LinkPair<short>) <=
                                kLinkLdsGroupBytes;
     // the schedule of this level
@@ -907,22 +936,19 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       Q.len_in = R.len_in;
       Q.ev_out = R.ev_out;
       Q.len_out = R.len_out;
-      if (R.pts && serial && k > opt.lds_levels && !lds_lane && !lds_group)
+      if (R.pts && serial && k > opt.lds_levels && !lds_lane && !lds_group && !pts_lds)
         hipLaunchKernelGGL(k_copy_links, dim3(grid_for(n)), dim3(256), 0, s, R.pv0, R.nx0, R.lk, n);
     }
     if (events) (void)hipEventRecord(events[2 * k], s);
     if (serial && k == 1) {
-      const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       hipLaunchKernelGGL(k_merge_level1, dim3(grid_for(bound), 2), dim3(256), 0, s, A);
     } else if (serial && k <= opt.lds_levels) {
-      const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 63) / 64), 2);
       if (k == 1) hipLaunchKernelGGL((k_merge_level_lds<PT, 2>), grid, dim3(64), 0, s, A);
       else if (k == 2) hipLaunchKernelGGL((k_merge_level_lds<PT, 4>), grid, dim3(64), 0, s, A);
       else if (k == 3) hipLaunchKernelGGL((k_merge_level_lds<PT, 8>), grid, dim3(64), 0, s, A);
       else hipLaunchKernelGGL((k_merge_level_lds<PT, 16>), grid, dim3(64), 0, s, A);
     } else if (serial) {
-      const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
       const dim3 grid((unsigned)((bound + 255) / 256), 2);
       LevelArgs B = A;
       if (k >= opt.order_from && bound >= opt.order_min) {
@@ -938,12 +964,16 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
       if (wave) {
         // lanes per merge double with every level (merges halve), so that
         // every lane-group level keeps about the same number of waves
-        const int per = 256 / lanes;  // merges per block
+        const int nb = pts_lds ? 64 : 256;  // lanes per block
+        const int per = nb / lanes;          // merges per block
         const dim3 wg((unsigned)((bound + per - 1) / per), 2);
-        const size_t lds = lds_group ? (size_t)per * A.width * sizeof(LinkPair<short>) : 0;
-#define HULL_WAVE(G)                                                                    \
-  if (lds_group) hipLaunchKernelGGL((k_merge_wave<PT, G, true>), wg, dim3(256), lds, s, B); \
-  else hipLaunchKernelGGL((k_merge_wave<PT, G, false>), wg, dim3(256), 0, s, B);
+        const size_t lds =
+            pts_lds ? (size_t)per * A.width * (sizeof(LinkPair<short>) + sizeof(PT))
+                    : (lds_group ? (size_t)per * A.width * sizeof(LinkPair<short>) : 0);
+#define HULL_WAVE(G)                                                                        \
+  if (pts_lds) hipLaunchKernelGGL((k_merge_wave<PT, G, 2>), wg, dim3(64), lds, s, B);         \
+  else if (lds_group) hipLaunchKernelGGL((k_merge_wave<PT, G, 1>), wg, dim3(256), lds, s, B); \
+  else hipLaunchKernelGGL((k_merge_wave<PT, G, 0>), wg, dim3(256), 0, s, B);
         if (lanes == 64) { HULL_WAVE(64) }
         else if (lanes == 32) { HULL_WAVE(32) }
         else if (lanes == 16) { HULL_WAVE(16) }

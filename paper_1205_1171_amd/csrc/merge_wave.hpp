@@ -64,19 +64,34 @@ __device__ inline double group_bcast(double x, int src) {
   }
 }
 
-// With LDSL the merge's working links sit in LDS as block-local int16 ranks
+// An event with its three ranks lowered by base (the kind bit above the
+// middle rank is kept: the rank stays at least base).
+__device__ __forceinline__ Event shift_event(Event E, int base) {
+  E.a -= base;
+  E.wk -= base;
+  E.b -= base;
+  return E;
+}
+
+// MODE 0: the merge's working links in the level's global working array,
+// points global.  MODE 1: the working links in LDS as block-local int16 ranks
 // (dynamic LDS: 256 / G merges per block x width link pairs of 4 bytes),
-// loaded by the group from the -inf links; without, in the level's global
-// working array.
-template <class PT, int G, bool LDSL>
+// loaded by the group from the -inf links.  MODE 2: links and points in LDS,
+// the merge working in block-local ranks (events shifted on the way in and
+// out); blocks of 64 lanes, for levels of few, long merges whose iterations
+// wait on point loads (dynamic LDS: 64 / G merges x width x (4 + point
+// size) bytes).
+template <class PT, int G, int MODE>
 __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
   static_assert(G == 8 || G == 16 || G == 32 || G == 64, "lanes per merge");
+  static_assert(MODE >= 0 && MODE <= 2, "link and point placement");
+  constexpr int NB = MODE == 2 ? 64 : 256;  // lanes per block
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   // per group of the block: G events of each child movie
-  __shared__ Event chunk[256 / G][2][G];
+  __shared__ Event chunk[NB / G][2][G];
   const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
   const int gshift = (threadIdx.x & 63) & ~(G - 1);  // the group's first lane in the wave
-  const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int64_t g0 = (blockIdx.x * (int64_t)NB + threadIdx.x) / G;
   const RunPtrs& R = A.run[blockIdx.y];
   if (!R.pts || g0 >= A.S.moff[A.S.H]) return;  // the same for every lane of the group
   const int* perm = A.perm[blockIdx.y];
@@ -96,11 +111,15 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
     }
     return;
   }
-  const PT* pts = (const PT*)R.pts;
   const int zs = R.zs;
-  using LK = typename std::conditional<LDSL, LdsLinksShifted<short>, GlobalLinks>::type;
+  // ranks inside the loop are global ranks minus base
+  const int base = MODE == 2 ? (int)s : 0;
+  using LK = typename std::conditional<
+      MODE == 2, LdsLinks<short, 1>,
+      typename std::conditional<MODE == 1, LdsLinksShifted<short>, GlobalLinks>::type>::type;
   LK lk;
-  if constexpr (LDSL) {
+  const PT* pts;
+  if constexpr (MODE >= 1) {
     if (e - s > A.width || A.width > 32767) {
       if (lane == 0) {
         atomicCAS(&h->err, 0, HULL_EINTERNAL);
@@ -109,11 +128,24 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
       return;
     }
     lk.p = (LinkPair<short>*)dyn_lds + (int64_t)grp * A.width;
-    lk.base = (int)s;
-    for (int j = lane; j < (int)(e - s); j += G) lk.set((int)s + j, R.pv0[s + j], R.nx0[s + j]);
+    if constexpr (MODE == 2) {
+      PT* P = (PT*)((LinkPair<short>*)dyn_lds + (int64_t)(NB / G) * A.width) + (int64_t)grp * A.width;
+      const PT* src = (const PT*)R.pts + s;
+      for (int j = lane; j < (int)(e - s); j += G) {
+        P[j] = src[j];
+        const int pv = R.pv0[s + j], nx = R.nx0[s + j];
+        lk.set(j, pv == kNil ? kNil : pv - base, nx == kNil ? kNil : nx - base);
+      }
+      pts = P;
+    } else {
+      lk.base = (int)s;
+      for (int j = lane; j < (int)(e - s); j += G) lk.set((int)s + j, R.pv0[s + j], R.nx0[s + j]);
+      pts = (const PT*)R.pts;
+    }
     __builtin_amdgcn_wave_barrier();
   } else {
     lk.p = R.lk;
+    pts = (const PT*)R.pts;
   }
   const Event* Lev = R.ev_in + 2 * s;
   const Event* Rev = R.ev_in + 2 * m;
@@ -122,8 +154,9 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
   Event* Lc = chunk[grp][0];
   Event* Rc = chunk[grp][1];
 
-  // 1. bridge at t = -inf: every lane takes the same walk
-  int u = (int)m - 1, v = (int)m;
+  // 1. bridge at t = -inf: every lane takes the same walk (the working links
+  // hold the -inf links at the start of the merge)
+  int u = (int)(m - base) - 1, v = (int)(m - base);
   {
     PT Pu = pts[u], Pv = pts[v];
     for (int guard = 0;; ++guard) {
@@ -134,7 +167,7 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
         }
         return;
       }
-      int w = R.nx0[v];
+      int w = lk.get(v).y;
       if (w != kNil) {
         const PT Pw = pts[w];
         if (d_sign(Pu, Pv, Pw) < 0) {
@@ -143,7 +176,7 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
           continue;
         }
       }
-      w = R.pv0[u];
+      w = lk.get(u).x;
       if (w != kNil) {
         const PT Pw = pts[w];
         if (d_sign(Pw, Pu, Pv) < 0) {
@@ -180,8 +213,8 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
   bool valid = false;
   unsigned dirty = 0xF;  // bridge lanes 2..5 whose triple changed
   int i = 0, j = 0, k = 0;
-  if (lane < nL) Lc[lane] = Lev[lane];
-  if (lane < nR) Rc[lane] = Rev[lane];
+  if (lane < nL) Lc[lane] = shift_event(Lev[lane], base);
+  if (lane < nR) Rc[lane] = shift_event(Rev[lane], base);
   __builtin_amdgcn_wave_barrier();
   const int64_t iter_cap = (int64_t)nL + nR + 4 * (e - s) + 16;
   for (int64_t it = 0;; ++it) {
@@ -253,7 +286,7 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
       const int nq = win == 0 ? nL : nR;
       if (q % G == 0 && q < nq) {
         __builtin_amdgcn_wave_barrier();
-        if (q + lane < nq) (win == 0 ? Lc : Rc)[lane] = (win == 0 ? Lev : Rev)[q + lane];
+        if (q + lane < nq) (win == 0 ? Lc : Rc)[lane] = shift_event((win == 0 ? Lev : Rev)[q + lane], base);
         __builtin_amdgcn_wave_barrier();
       }
       // the event sets nx(a) and pv(b) (and, inserting w, both links of w);
@@ -287,14 +320,14 @@ __global__ void __launch_bounds__(256) k_merge_wave(LevelArgs A) {
         if (lane == 0) atomicCAS(&h->err, 0, HULL_EINTERNAL);
         break;
       }
-      if (lane == 0) out[k] = make_event(ba, bw, bb, bk, bs);
+      if (lane == 0) out[k] = make_event(ba + base, bw + base, bb + base, bk, bs);
       ++k;
     }
   }
   // 3. splice the -inf chains
   if (lane == 0) {
-    R.nx0[u0] = v0;
-    R.pv0[v0] = u0;
+    R.nx0[u0 + base] = v0 + base;
+    R.pv0[v0 + base] = u0 + base;
     R.len_out[s] = k;
   }
 }

@@ -76,6 +76,12 @@ STRATEGIES = {
     # and for any number of merges, lane-serial and lane groups
     "ordered": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "7",
                 "HULL_WAVE_LANES": "8", "HULL_ORDER_LEVEL": "4", "HULL_ORDER_MIN": "0"},
+    # lane groups with the merge's points in LDS too (block-local ranks) at
+    # every level where a block fits, and at none
+    "wave5_pts_lds": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
+                      "HULL_WAVE_LANES": "8", "HULL_PTS_LDS_MERGES": "1000000000"},
+    "wave5_no_pts_lds": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
+                         "HULL_WAVE_LANES": "16", "HULL_PTS_LDS_MERGES": "0"},
 }
 
 
@@ -222,7 +228,8 @@ def _golden(name):
 @pytest.mark.parametrize("name", ["cfg2_ball", "cfg2_sphere", "cfg3"])
 def test_full_size_digest(H, ws, name):
     for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
-              "HULL_LDS_LINKS", "HULL_LDS_LEVELS", "HULL_ORDER_LEVEL", "HULL_ORDER_MIN"):
+              "HULL_LDS_LINKS", "HULL_LDS_LEVELS", "HULL_ORDER_LEVEL", "HULL_ORDER_MIN",
+              "HULL_PTS_LDS_MERGES"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
