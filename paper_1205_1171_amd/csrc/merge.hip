@@ -741,6 +741,7 @@ __global__ void __launch_bounds__(256)
 
 // Lane-serial levels whose blocks (2, 4, 8, 16 points) are staged in LDS.
 constexpr int kLdsLevels = 4;
+constexpr int kFirstWaveLevel = 4;
 
 static int levels_for(int64_t n) {
   int L = 0;
@@ -779,11 +780,12 @@ struct Opts {
 // The first lane-group level when the caller gives none: lane groups pay
 // once a level's merges are too few to fill the chip one lane each (they
 // then get several lanes), so the fewer points a call has in all, the lower
-// the level -- level 5 up to 2^18 points, one level later per doubling, level
-// 8 from 2^21 (measured on cubes and spheres of 2^11..2^20 points and on
-// the n = 2^24 workload).
+// the level -- level 4 up to 2^16 points, 5 up to 2^18, one level later per
+// doubling, level 8 from 2^21 (measured on cubes and spheres of 2^11..2^20
+// points and on the n = 2^24 workload).
 static int default_wave_level(int64_t total) {
-  return std::min(8, std::max(kLdsLevels + 1, levels_for(total) - 13));
+  const int L = levels_for(total);
+  return L <= 16 ? kFirstWaveLevel : std::min(8, std::max(5, L - 13));
 }
 
 static Opts resolve(const hull_schedule_t* sc, int64_t total) {
@@ -791,13 +793,14 @@ static Opts resolve(const hull_schedule_t* sc, int64_t total) {
   o.serial_max = sc && sc->serial_levels >= 0 ? sc->serial_levels : env_int("HULL_SERIAL_LEVELS", 10);
   o.seg = sc && sc->walk_segment > 0 ? sc->walk_segment : env_int("HULL_WALK_SEGMENT", 4);
   if (o.seg < kMinWalkSegment) o.seg = kMinWalkSegment;
+  o.lds_levels = std::min(std::max(env_int("HULL_LDS_LEVELS", 3), 0), kLdsLevels);
   const int wf = sc && sc->wave_from != 0 ? sc->wave_from
                                           : env_int("HULL_WAVE_LEVEL", default_wave_level(total));
-  o.wave_from = wf > 0 ? std::max(wf, kLdsLevels + 1) : 0;
+  // lane groups start above the LDS-staged levels, at level 4 (16 points) at the earliest
+  o.wave_from = wf > 0 ? std::max(wf, std::max(o.lds_levels + 1, kFirstWaveLevel)) : 0;
   const int wl = sc && sc->wave_lanes > 0 ? sc->wave_lanes : env_int("HULL_WAVE_LANES", 8);
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
   o.lds_links = env_int("HULL_LDS_LINKS", 1) != 0;
-  o.lds_levels = std::min(std::max(env_int("HULL_LDS_LEVELS", 3), 0), kLdsLevels);
   o.order_from = env_int("HULL_ORDER_LEVEL", kOrderFromLevel);
   o.order_min = std::max(env_int("HULL_ORDER_MIN", (int)kOrderMinMerges), 0);
   o.pts_lds_merges = std::max(env_int("HULL_PTS_LDS_MERGES", kPtsLdsMerges), 0);

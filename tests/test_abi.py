@@ -164,8 +164,11 @@ def test_schedule_defaults(L, monkeypatch):
     monkeypatch.setenv("HULL_LDS_LEVELS", "0")
     assert hull.schedule_defaults().fused_levels == 0
     monkeypatch.delenv("HULL_LDS_LEVELS")
-    monkeypatch.setenv("HULL_WAVE_LEVEL", "2")  # raised above the levels LDS staging can take
+    monkeypatch.setenv("HULL_WAVE_LEVEL", "2")  # raised above the LDS-staged levels (3), to 4
+    assert hull.schedule_defaults().wave_from == 4
+    monkeypatch.setenv("HULL_LDS_LEVELS", "4")
     assert hull.schedule_defaults().wave_from == 5
+    monkeypatch.delenv("HULL_LDS_LEVELS")
     monkeypatch.setenv("HULL_WAVE_LEVEL", "-1")
     assert hull.schedule_defaults().wave_from == 0
     monkeypatch.delenv("HULL_WAVE_LEVEL")

@@ -80,6 +80,8 @@ STRATEGIES = {
     # every level where a block fits, and at none
     "wave5_pts_lds": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
                       "HULL_WAVE_LANES": "8", "HULL_PTS_LDS_MERGES": "1000000000"},
+    "wave4": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "4",
+              "HULL_WAVE_LANES": "8"},
     "wave5_no_pts_lds": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
                          "HULL_WAVE_LANES": "16", "HULL_PTS_LDS_MERGES": "0"},
 }
