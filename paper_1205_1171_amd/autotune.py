@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned_schedules.json")
 
 SERIAL_LEVELS = (8, 9, 10, 11, 12, 13, 14, 99)
-WALK_SEGMENTS = (8, 16, 32)
+WALK_SEGMENTS = (4, 8, 16, 32)
 WAVE_LEVELS = (-1, 5, 6, 7, 8, 9)  # -1: no lane groups
 WAVE_LANES = 8
 
