@@ -321,7 +321,8 @@ def single(args, hull, workloads):
                    "schedule": {"serial_levels": sched.serial_levels,
                                 "walk_segment": sched.walk_segment,
                                 "wave_from": sched.wave_from,
-                                "wave_lanes": sched.wave_lanes}},
+                                "wave_lanes": sched.wave_lanes,
+                                "wave_lanes_max": sched.wave_lanes_max}},
         "bit_exact": bit_exact,
         "phase_ms": {"sort": round(sort_ms, 4), "merge_levels": [round(v, 4) for v in lvl],
                      "extract": round(extract_ms, 4)},
@@ -522,6 +523,7 @@ def batched(hull, workloads, autotune, reps, per_hull=True):
         "hulls": H, "points": N, "faces": int(face_off[-1]),
         "schedule": {"serial_levels": s.serial_levels, "walk_segment": s.walk_segment,
                      "wave_from": s.wave_from, "wave_lanes": s.wave_lanes,
+                     "wave_lanes_max": s.wave_lanes_max,
                      "source": "autotuner cache" if sched is not None else "library defaults"},
         "ms_graph": round(ms_graph, 3), "ms_eager": round(ms_eager, 3),
         "ms_one_launch_per_hull": round(ms_loop, 3) if ms_loop else None,

@@ -152,20 +152,24 @@ int32_t hull_full_noalloc(const int32_t* d_xyz, int64_t n, int32_t* d_faces, int
  *   wave_from      lane-serial levels from this one on run one merge per
  *                  group of wave_lanes lanes instead of one per lane (the
  *                  six candidates of an iteration on six lanes, child movies
- *                  through LDS); 0: the default (level 5 for calls of up to
- *                  2^18 points in all, one level later per doubling, level 8
- *                  from 2^21 points), negative: no level
+ *                  through LDS); 0: the default (level 4 for calls of up to
+ *                  2^16 points in all, 5 up to 2^18, one level later per
+ *                  doubling, level 8 from 2^21 points), negative: no level
  *   wave_lanes     lanes per merge at level wave_from: 8, 16, 32 or 64,
- *                  doubling with every level above (merges halve), up to 64
- *                  (0: the default, 8)
- *   reserved       pass 0 */
+ *                  doubling with every level above (merges halve), up to
+ *                  wave_lanes_max (0: the default, 8)
+ *   wave_lanes_max the most lanes per merge: 8, 16, 32 or 64, at least
+ *                  wave_lanes (0: the default, 64; environment
+ *                  HULL_WAVE_LANES_MAX).  Batches with many long merges on
+ *                  the top lane-serial levels keep more merges in flight
+ *                  with fewer lanes each. */
 typedef struct hull_schedule_t {
   int32_t serial_levels;
   int32_t walk_segment;
   int32_t fused_levels;
   int32_t wave_from;
   int32_t wave_lanes;
-  int32_t reserved;
+  int32_t wave_lanes_max;
 } hull_schedule_t;
 
 /* The schedule the library uses when a call passes none (or leaves a field

@@ -768,6 +768,7 @@ struct Opts {
   int serial_max, seg;
   int wave_from;   // first lane-serial level run by lane groups (0: none)
   int wave_lanes;  // lanes per merge at level wave_from (8, 16, 32 or 64), doubling per level
+  int wave_lanes_max;  // ... up to this many
   bool lds_links;  // working links in LDS where they fit (HULL_LDS_LINKS=0: global)
   int lds_levels;  // lowest levels with points and links staged in LDS (at most kLdsLevels;
                    // above them, the links alone)
@@ -800,6 +801,8 @@ static Opts resolve(const hull_schedule_t* sc, int64_t total) {
   o.wave_from = wf > 0 ? std::max(wf, std::max(o.lds_levels + 1, kFirstWaveLevel)) : 0;
   const int wl = sc && sc->wave_lanes > 0 ? sc->wave_lanes : env_int("HULL_WAVE_LANES", 8);
   o.wave_lanes = wl >= 64 ? 64 : (wl >= 32 ? 32 : (wl >= 16 ? 16 : 8));
+  const int wm = sc && sc->wave_lanes_max > 0 ? sc->wave_lanes_max : env_int("HULL_WAVE_LANES_MAX", 64);
+  o.wave_lanes_max = std::max(o.wave_lanes, wm >= 64 ? 64 : (wm >= 32 ? 32 : (wm >= 16 ? 16 : 8)));
   o.lds_links = env_int("HULL_LDS_LINKS", 1) != 0;
   o.order_from = env_int("HULL_ORDER_LEVEL", kOrderFromLevel);
   o.order_min = std::max(env_int("HULL_ORDER_MIN", (int)kOrderMinMerges), 0);
@@ -897,7 +900,8 @@ static int32_t run_levels(int64_t n, const Sched& S0, char* ws, const Plan& pl, 
     const bool serial = k <= opt.serial_max;
     // lane groups at this level, and where the working links live
     const bool wave = serial && k > opt.lds_levels && opt.wave_from > 0 && k >= opt.wave_from;
-    const int lanes = wave ? std::min(64, opt.wave_lanes << std::min(k - opt.wave_from, 3)) : 0;
+    const int lanes =
+        wave ? std::min(opt.wave_lanes_max, opt.wave_lanes << std::min(k - opt.wave_from, 3)) : 0;
     const bool lds_lane = serial && k > opt.lds_levels && !wave && opt.lds_links &&
                           A.width <= kLinkLdsLane;
     const int64_t bound = std::min<int64_t>(pl.mcap, n / A.width + S.H + 1);
@@ -1195,7 +1199,7 @@ int32_t hull_schedule_defaults(hull_schedule_t* out) {
   out->fused_levels = o.lds_levels;
   out->wave_from = o.wave_from;
   out->wave_lanes = o.wave_lanes;
-  out->reserved = 0;
+  out->wave_lanes_max = o.wave_lanes_max;
   return HULL_OK;
 }
 

@@ -24,12 +24,12 @@ class Schedule(ctypes.Structure):
     """hull_schedule_t: merge schedule of a batched call (-1 / 0 = default)."""
     _fields_ = [("serial_levels", ctypes.c_int32), ("walk_segment", ctypes.c_int32),
                 ("fused_levels", ctypes.c_int32), ("wave_from", ctypes.c_int32),
-                ("wave_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("wave_lanes", ctypes.c_int32), ("wave_lanes_max", ctypes.c_int32)]
 
     def __init__(self, serial_levels=-1, walk_segment=0, fused_levels=-1, wave_from=0,
-                 wave_lanes=0):
+                 wave_lanes=0, wave_lanes_max=0):
         super().__init__(int(serial_levels), int(walk_segment), int(fused_levels), int(wave_from),
-                         int(wave_lanes), 0)
+                         int(wave_lanes), int(wave_lanes_max))
 
 
 class HullError(RuntimeError):

@@ -153,10 +153,11 @@ def test_schedule_defaults(L, monkeypatch):
     """Built-in defaults, the environment overrides, and the number of
     LDS-staged levels reported in fused_levels."""
     for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
-              "HULL_LDS_LEVELS"):
+              "HULL_LDS_LEVELS", "HULL_WAVE_LANES_MAX"):
         monkeypatch.delenv(k, raising=False)
     s = hull.schedule_defaults()
     assert (s.serial_levels, s.walk_segment, s.wave_from, s.wave_lanes) == (10, 4, 8, 8)
+    assert s.wave_lanes_max == 64
     assert 0 <= s.fused_levels <= s.serial_levels
     assert s.fused_levels == 3
     monkeypatch.setenv("HULL_LDS_LEVELS", "9")  # at most 4 levels stage points in LDS
@@ -174,6 +175,12 @@ def test_schedule_defaults(L, monkeypatch):
     monkeypatch.delenv("HULL_WAVE_LEVEL")
     monkeypatch.setenv("HULL_WAVE_LANES", "64")
     assert hull.schedule_defaults().wave_lanes == 64
+    monkeypatch.setenv("HULL_WAVE_LANES_MAX", "8")  # never below the first level's lanes
+    assert hull.schedule_defaults().wave_lanes_max == 64
+    monkeypatch.setenv("HULL_WAVE_LANES", "16")
+    monkeypatch.setenv("HULL_WAVE_LANES_MAX", "20")  # rounded down to a lane count
+    assert hull.schedule_defaults().wave_lanes_max == 16
+    monkeypatch.delenv("HULL_WAVE_LANES_MAX")
     monkeypatch.delenv("HULL_WAVE_LANES")
     monkeypatch.setenv("HULL_SERIAL_LEVELS", "12")
     monkeypatch.setenv("HULL_WALK_SEGMENT", "32")

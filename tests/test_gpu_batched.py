@@ -206,14 +206,15 @@ def test_autotuner_schedules_agree(H, ws):
     pts, off, _ = workloads.cfg4(H=120, lo=3.0, hi=13.0)
     x = torch.from_numpy(pts).cuda()
     best, times = autotune.tune(x, off, reps=1, serial_levels=(6, 9, 99), walk_segments=(8, 32),
-                                wave_levels=(-1, 7), save=False, log=say)
-    assert (best.serial_levels, best.walk_segment, best.wave_from) in times
+                                wave_levels=(-1, 7), wave_lanes_max=(8, 64), save=False, log=say)
+    assert (best.serial_levels, best.walk_segment, best.wave_from, best.wave_lanes_max) in times
+    assert all(cap == 64 for sl, seg, wf, cap in times if wf < 0)
     ref = None
-    for sl, seg, wf in times:
-        f, fo = H.hull_batched_sync(x, off, schedule=H.Schedule(sl, seg, 0, wf, 16), ws=ws)
+    for sl, seg, wf, cap in times:
+        f, fo = H.hull_batched_sync(x, off, schedule=H.Schedule(sl, seg, 0, wf, 8, cap), ws=ws)
         cur = [validate.canonical(f[fo[h]:fo[h + 1]].cpu().numpy()) for h in range(len(off) - 1)]
         if ref is None:
             ref = cur
         else:
             assert all(a.shape == b.shape and (a == b).all() for a, b in zip(ref, cur)), \
-                (sl, seg, wf)
+                (sl, seg, wf, cap)

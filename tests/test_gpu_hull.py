@@ -80,6 +80,9 @@ STRATEGIES = {
     # every level where a block fits, and at none
     "wave5_pts_lds": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
                       "HULL_WAVE_LANES": "8", "HULL_PTS_LDS_MERGES": "1000000000"},
+    # lane groups that stay at 8 lanes per merge on every level (lane cap)
+    "wave5_cap8": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
+                   "HULL_WAVE_LANES": "8", "HULL_WAVE_LANES_MAX": "8"},
     "wave4": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "4",
               "HULL_WAVE_LANES": "8"},
     "wave5_no_pts_lds": {"HULL_SERIAL_LEVELS": "99", "HULL_WALK_SEGMENT": "", "HULL_WAVE_LEVEL": "5",
@@ -231,7 +234,7 @@ def _golden(name):
 def test_full_size_digest(H, ws, name):
     for k in ("HULL_SERIAL_LEVELS", "HULL_WALK_SEGMENT", "HULL_WAVE_LEVEL", "HULL_WAVE_LANES",
               "HULL_LDS_LINKS", "HULL_LDS_LEVELS", "HULL_ORDER_LEVEL", "HULL_ORDER_MIN",
-              "HULL_PTS_LDS_MERGES"):
+              "HULL_PTS_LDS_MERGES", "HULL_WAVE_LANES_MAX"):
         os.environ.pop(k, None)
     rec = _golden(name)
     p = getattr(workloads, name)()
