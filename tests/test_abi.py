@@ -253,3 +253,15 @@ def test_workspace_limits(L):
     assert L.hull_workspace_bytes_batched((1 << 28) + 1, 10000, ctypes.byref(out)) == hull.HULL_EINVAL
     assert L.hull_workspace_bytes((1 << 26), 0, ctypes.byref(out)) == hull.HULL_OK
     assert out.value < 288e9
+
+
+def test_schedule_struct_matches_header():
+    """The binding's hull_schedule_t has the header's fields, in its order,
+    all int32 (the library reads them by offset)."""
+    src = open(os.path.join(ROOT, "include", "hull3d.h")).read()
+    body = re.search(r"typedef struct hull_schedule_t \{(.*?)\} hull_schedule_t;", src, flags=re.S)
+    assert body
+    fields = re.findall(r"int32_t\s+([a-z_]+);", body.group(1))
+    assert [f for f, _ in hull.Schedule._fields_] == fields
+    assert all(t is ctypes.c_int32 for _, t in hull.Schedule._fields_)
+    assert ctypes.sizeof(hull.Schedule) == 4 * len(fields)
